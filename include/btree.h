@@ -1,0 +1,163 @@
+/*
+ * btree.h -- C ABI of the MI355X (gfx950) b-tree neighbour search.
+ *
+ * Method: Cavelan, Cabezon, Korndorfer, Ciorba, "Finding Neighbors in a
+ * Forest: A b-tree for Smoothed Particle Hydrodynamics Simulations"
+ * (arXiv 1910.02639).  BuildTree is Algorithm 1 with Eqs. 1-4 (Section 3.1);
+ * FindNeighbors is Algorithm 2 with Eq. 5 (Section 3.2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Particle data (x, y, z, h), counts, offsets and nbrs are DEVICE
+ *    pointers owned by the caller.  They must stay valid until the work
+ *    queued on `hip_stream` has run.  The library never frees them and keeps
+ *    no pointer to them after a call returns.
+ *  - `hip_stream` is a hipStream_t passed as void* (NULL = null stream).
+ *    All device work of a call is queued on that stream.
+ *  - Coordinates and smoothing lengths are FP64, structure-of-arrays, one
+ *    entry per particle, indexed 0..n-1 ("original index").
+ *  - Every call returns a btree_status.  On failure the thread-local message
+ *    of btree_last_error() says why.  No C++ exception crosses the ABI.
+ *  - Host-side argument checks (NULL pointers, negative sizes, bad
+ *    parameters) run before anything is queued.  Data checks (non-finite
+ *    coordinates, h < 0 or non-finite) run on the device; when they fail the
+ *    call returns BTREE_EINVAL and no caller-owned output has been written.
+ *  - Distinct handles may be used from distinct host threads at once.  One
+ *    handle must not be used by two threads at once.
+ */
+#ifndef BTREE_H
+#define BTREE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    BTREE_OK = 0,
+    BTREE_EINVAL = -1,     /* bad argument or bad particle data            */
+    BTREE_ENOMEM = -2,     /* a device allocation failed                    */
+    BTREE_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed    */
+    BTREE_EOVERFLOW = -4,  /* caller's output capacity below the total      */
+    BTREE_ESTATE = -5      /* call made in a state that does not allow it   */
+} btree_status;
+
+typedef enum {
+    BTREE_FP64 = 0,        /* every pair tested with the FP64 predicate     */
+    BTREE_FP32_FILTER = 1  /* FP32 test with a rounding margin; pairs inside
+                              the margin re-tested with the FP64 predicate  */
+} btree_precision;
+
+/* Tree and search parameters (Table 1 of the paper for s, alpha, beta). */
+typedef struct {
+    int32_t bucket_size;    /* s: a cell with more than s particles is split;
+                               default 64, must be >= 1                       */
+    double  alpha;          /* alpha: a sub-cell is "under-filled" when it
+                               holds fewer than alpha*s particles (Eq. 4);
+                               default 0.5, must be finite and >= 0           */
+    double  beta;           /* beta: b is halved while the fraction of
+                               under-filled sub-cells exceeds beta (Eq. 4);
+                               default 0.5, must be finite                    */
+    int32_t max_depth;      /* depth guard: a cell at this depth is a leaf
+                               whatever its size; default 32, 0..64           */
+    int32_t precision;      /* btree_precision; default BTREE_FP32_FILTER     */
+    int32_t group_size;     /* queries per wavefront work item, 0 = library
+                               choice (64); must be 0 or 64                   */
+    int32_t reserved[6];    /* must be zero                                   */
+} btree_params;
+
+/* Shape of a built tree and counters of the last search. */
+typedef struct {
+    int64_t n;              /* particles                                      */
+    int64_t n_internal;     /* internal cells (split by Algorithm 1)          */
+    int64_t n_leaves;       /* non-empty leaf cells                           */
+    int64_t depth;          /* deepest leaf; the root is depth 0              */
+    int64_t rounds;         /* halvings of b over all internal cells (Eq. 4)  */
+    int64_t max_leaf;       /* largest leaf                                   */
+    int64_t oversized;      /* leaves above s (made by the depth guard)       */
+    int64_t n_chunks;       /* wavefront work items of the search             */
+    int64_t b_hist[65];     /* b_hist[b] = internal cells with branching b,
+                               b >= 64 counted in b_hist[64]                  */
+    /* counters of the last btree_find_neighbors pass 1 on this handle:     */
+    int64_t total;          /* neighbour entries                              */
+    int64_t pair_tests;     /* candidate pairs tested (FP32 or FP64)          */
+    int64_t fp64_confirms;  /* FP32-filter pairs re-tested in FP64            */
+    int64_t brute_chunks;   /* work items that took the exhaustive path       */
+    int64_t candidates;     /* culled candidates staged, summed over items    */
+} btree_stats_t;
+
+typedef struct btree_tree* btree_handle;
+
+/* Fills *p with the defaults listed in btree_params.
+ * Returns BTREE_EINVAL if p is NULL. */
+btree_status btree_params_default(btree_params* p);
+
+/* BuildTree (Algorithm 1, Eqs. 1-4).
+ * x, y, z: device FP64 coordinates of n particles (n >= 0, n < 2^31).
+ * p: parameters (NULL = defaults).  On success *out receives a handle that
+ * owns a sorted copy of the particles and the tree; release it with
+ * btree_destroy.  The root cell is the tight bounding box of the particles;
+ * each cell is split into b^3 equal sub-cells, b from Eq. 1 halved while the
+ * Eq. 4 ratio exceeds beta (b >= 2); sub-cells holding more than s
+ * particles are split again; empty sub-cells are not stored.
+ * Synchronises `hip_stream` (the level loop reads node counts on the host).
+ * Errors: EINVAL (NULL x/y/z/out with n > 0, n < 0 or n >= 2^31, bad
+ * parameters, non-finite coordinate), ENOMEM, EDEVICE. */
+btree_status btree_build(const double* x, const double* y, const double* z,
+                         int64_t n, const btree_params* p, void* hip_stream,
+                         btree_handle* out);
+
+/* FindNeighbors (Algorithm 2, Eq. 5) for every particle of the tree.
+ * Row i lists, in ascending original index, every j with
+ *     ((dx*dx + dy*dy) + dz*dz) < (2*h_i)*(2*h_i),
+ *     dx = x_i - x_j (likewise dy, dz), FP64, each operation rounded,
+ * i.e. the query particle's own radius 2h_i (gather form; i itself is listed
+ * when h_i > 0).  Results are identical for every precision and parameter.
+ *
+ * h: device FP64 smoothing lengths (n entries, finite, >= 0).
+ * counts: device int32[n], row lengths.
+ * offsets: device int64[n+1], offsets[0] = 0, offsets[i+1] = offsets[i] +
+ *          counts[i]; row i occupies nbrs[offsets[i] .. offsets[i+1]).
+ * nbrs: device int32[capacity] or NULL.
+ * total: host int64, receives offsets[n].
+ *
+ * Pass 1 (nbrs == NULL): writes counts, offsets and *total; synchronises
+ *   the stream.  Remembers h, counts and offsets for pass 2.
+ * Pass 2 (nbrs != NULL, right after pass 1 on this handle with the same h,
+ *   counts and offsets, whose contents the caller has not changed): writes
+ *   nbrs[0..total) and *total, without synchronising.
+ * Otherwise (nbrs != NULL, no matching pass 1): runs both passes.
+ * Errors: EINVAL (NULL h/counts/offsets/total with n > 0, bad h values),
+ *   EOVERFLOW (capacity < total; nbrs untouched), ESTATE (NULL handle),
+ *   ENOMEM, EDEVICE. */
+btree_status btree_find_neighbors(btree_handle t, const double* h,
+                                  int32_t* counts, int64_t* offsets,
+                                  int32_t* nbrs, int64_t capacity,
+                                  int64_t* total, void* hip_stream);
+
+/* Tree shape and last-search counters.  Errors: EINVAL (NULL argument). */
+btree_status btree_stats(btree_handle t, btree_stats_t* out);
+
+/* Copies the leaf layout to HOST arrays (for inspection and tests):
+ * leaf_beg[n_leaves], leaf_cnt[n_leaves], leaf_depth[n_leaves] in memory
+ * order (depth-first, sub-cells in Morton order of their coordinates), and
+ * order[n] = original index of the particle at each sorted position.  Any
+ * pointer may be NULL to skip that array.  Synchronises `hip_stream`.
+ * Errors: EINVAL (NULL handle), EDEVICE. */
+btree_status btree_export(btree_handle t, int32_t* leaf_beg, int32_t* leaf_cnt,
+                          int32_t* leaf_depth, int32_t* order,
+                          void* hip_stream);
+
+/* Releases the handle and all device memory it owns (NULL is a no-op).
+ * Waits for work the handle queued to finish first. */
+btree_status btree_destroy(btree_handle t);
+
+/* Message of the last failed call on this host thread ("" if none). */
+const char* btree_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BTREE_H */

@@ -1,0 +1,198 @@
+"""CPU oracle for the b-tree neighbour search (arXiv 1910.02639).
+
+TEST INFRASTRUCTURE ONLY.  The test suite, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` are the only callers.  Nothing here is
+shared with, imported by, or imports the GPU library.
+
+The arithmetic lives in ``oracle.c`` (plain C, FP64, no FMA contraction):
+
+* ``lists`` / ``counts`` / ``row``: the definition of FindNeighbors' result
+  (Section 3.2, Algorithm 2): for each query i, every j with
+  ``((dx*dx + dy*dy) + dz*dz) < (2*h_i)*(2*h_i)``, ascending in j.
+* ``build_tree``: Algorithm 1 (BuildTree) with Eqs. 1-4, as a recursion in
+  the paper's order, reporting the tree shape and each leaf's members in a
+  canonical depth-first order.
+* ``eq1_branching``, ``eq2_subcell``, ``eq3_cell_id``, ``eq5_range``: the
+  equations of Section 3, one function each.
+
+Parity is pinned by tests/test_oracle.py against closed forms, the paper's
+worked examples, invariants and an independent k-d tree (scipy).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "_oracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into _oracle.so (gcc, -ffp-contract=off, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp",
+               "-shared", "-fPIC", "-std=c11", _SRC, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        lib = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        D = ctypes.c_double
+        lib.oracle_pair.restype = ctypes.c_int
+        lib.oracle_pair.argtypes = [D] * 7
+        lib.oracle_row.restype = I64
+        lib.oracle_row.argtypes = [P, P, P, P, I64, I64, P, I64]
+        lib.oracle_counts.restype = None
+        lib.oracle_counts.argtypes = [P, P, P, P, I64, P, I64, P]
+        lib.oracle_lists.restype = I64
+        lib.oracle_lists.argtypes = [P, P, P, P, I64, P, I64, P, P, I64]
+        lib.oracle_eq1_branching.restype = I64
+        lib.oracle_eq1_branching.argtypes = [I64, I64]
+        lib.oracle_eq2_subcell.restype = I64
+        lib.oracle_eq2_subcell.argtypes = [D, D, D, I64]
+        lib.oracle_eq3_cell_id.restype = I64
+        lib.oracle_eq3_cell_id.argtypes = [I64, I64, I64, I64]
+        lib.oracle_eq5_range.restype = None
+        lib.oracle_eq5_range.argtypes = [D, D, D, D, I64, P, P]
+        lib.oracle_build_tree.restype = None
+        lib.oracle_build_tree.argtypes = [P, P, P, I64, I64, D, D, ctypes.c_int32,
+                                          P, P, I64, P, P, I64, P, P, P, I64, P]
+        _lib = lib
+    return _lib
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def pair(xi, yi, zi, hi, xj, yj, zj) -> bool:
+    """P64(i, j) for one pair of points."""
+    return bool(_load().oracle_pair(xi, yi, zi, hi, xj, yj, zj))
+
+
+def row(x, y, z, h, i: int) -> np.ndarray:
+    """Row i of the neighbour lists (ascending original indices)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.shape[0]
+    lib = _load()
+    k = lib.oracle_row(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, int(i), None, 0)
+    out = np.empty(max(k, 1), dtype=np.int32)
+    lib.oracle_row(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, int(i), _ptr(out), k)
+    return out[:k]
+
+
+def counts(x, y, z, h, rows=None) -> np.ndarray:
+    """Neighbour counts (int64) of the given rows (all rows by default)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.shape[0]
+    if rows is None:
+        m, rp = n, None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        m, rp = rows.shape[0], _ptr(rows)
+    out = np.empty(max(m, 1), dtype=np.int64)
+    _load().oracle_counts(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, rp, m, _ptr(out))
+    return out[:m]
+
+
+def lists(x, y, z, h, rows=None):
+    """CSR lists of the given rows: (counts int64, offsets int64, nbrs int32)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.shape[0]
+    if rows is None:
+        m, rp = n, None
+    else:
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        m, rp = rows.shape[0], _ptr(rows)
+    c = counts(x, y, z, h, rows)
+    total = int(c.sum())
+    offsets = np.empty(m + 1, dtype=np.int64)
+    nbrs = np.empty(max(total, 1), dtype=np.int32)
+    got = _load().oracle_lists(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, rp, m,
+                               _ptr(offsets), _ptr(nbrs), total)
+    assert got == total
+    return c, offsets, nbrs[:total]
+
+
+def eq1_branching(n: int, s: int) -> int:
+    return int(_load().oracle_eq1_branching(int(n), int(s)))
+
+
+def eq2_subcell(x: float, lo: float, hi: float, b: int) -> int:
+    return int(_load().oracle_eq2_subcell(float(x), float(lo), float(hi), int(b)))
+
+
+def eq3_cell_id(c1: int, c2: int, c3: int, b: int) -> int:
+    return int(_load().oracle_eq3_cell_id(int(c1), int(c2), int(c3), int(b)))
+
+
+def eq5_range(x: float, R: float, lo: float, hi: float, b: int):
+    a = ctypes.c_int64()
+    c = ctypes.c_int64()
+    _load().oracle_eq5_range(float(x), float(R), float(lo), float(hi), int(b),
+                             ctypes.byref(a), ctypes.byref(c))
+    return a.value, c.value
+
+
+class Tree:
+    """Result of Algorithm 1: shape statistics and canonical leaves."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    def leaf_offsets(self) -> np.ndarray:
+        off = np.zeros(self.n_leaves + 1, dtype=np.int64)
+        np.cumsum(self.leaf_cnt, out=off[1:])
+        return off
+
+
+def build_tree(x, y, z, s: int = 64, alpha: float = 0.5, beta: float = 0.5,
+               max_depth: int = 32) -> Tree:
+    """Algorithm 1 on all particles; leaves in canonical depth-first order
+    (sub-cells in Morton order of their coordinates), members ascending."""
+    x, y, z = map(_f64, (x, y, z))
+    n = x.shape[0]
+    leaf_cap = max(n, 1)
+    node_cap = max(n, 1)
+    bh_len = 1 << 16
+    leaf_cnt = np.zeros(leaf_cap, dtype=np.int64)
+    leaf_depth = np.zeros(leaf_cap, dtype=np.int32)
+    members = np.zeros(max(n, 1), dtype=np.int32)
+    b_hist = np.zeros(bh_len, dtype=np.int64)
+    node_b = np.zeros(node_cap, dtype=np.int32)
+    node_n = np.zeros(node_cap, dtype=np.int64)
+    node_depth = np.zeros(node_cap, dtype=np.int32)
+    stats = np.zeros(8, dtype=np.int64)
+    _load().oracle_build_tree(_ptr(x), _ptr(y), _ptr(z), n, int(s), float(alpha),
+                              float(beta), int(max_depth), _ptr(leaf_cnt),
+                              _ptr(leaf_depth), leaf_cap, _ptr(members),
+                              _ptr(b_hist), bh_len, _ptr(node_b), _ptr(node_n),
+                              _ptr(node_depth), node_cap, _ptr(stats))
+    if stats[6]:
+        raise RuntimeError("oracle build_tree: capacity exceeded")
+    ni, nl = int(stats[0]), int(stats[1])
+    bh = {int(b): int(c) for b, c in enumerate(b_hist) if c}
+    return Tree(n_internal=ni, n_leaves=nl, depth=int(stats[2]),
+                rounds=int(stats[3]), max_leaf=int(stats[4]),
+                leaf_cnt=leaf_cnt[:nl].copy(), leaf_depth=leaf_depth[:nl].copy(),
+                members=members[:int(stats[5])].copy(), b_hist=bh,
+                node_b=node_b[:ni].copy(), node_n=node_n[:ni].copy(),
+                node_depth=node_depth[:ni].copy())
