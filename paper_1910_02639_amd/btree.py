@@ -1,0 +1,230 @@
+"""Python binding of libbtree (include/btree.h): argument marshalling only.
+
+Every step of the search runs in the HIP library; this module only checks
+tensor dtypes/devices, allocates outputs with torch and forwards raw device
+pointers and the current HIP stream.  There is no fallback: if libbtree.so
+is missing or cannot be loaded, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbtree.so")
+
+BTREE_OK = 0
+BTREE_EINVAL = -1
+BTREE_ENOMEM = -2
+BTREE_EDEVICE = -3
+BTREE_EOVERFLOW = -4
+BTREE_ESTATE = -5
+BTREE_FP64 = 0
+BTREE_FP32_FILTER = 1
+
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW",
+                -5: "ESTATE"}
+
+SYMBOLS = ["btree_params_default", "btree_build", "btree_find_neighbors", "btree_stats",
+           "btree_export", "btree_destroy", "btree_last_error"]
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("bucket_size", ctypes.c_int32), ("alpha", ctypes.c_double),
+                ("beta", ctypes.c_double), ("max_depth", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("group_size", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("n_internal", ctypes.c_int64),
+                ("n_leaves", ctypes.c_int64), ("depth", ctypes.c_int64),
+                ("rounds", ctypes.c_int64), ("max_leaf", ctypes.c_int64),
+                ("oversized", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
+                ("b_hist", ctypes.c_int64 * 65), ("total", ctypes.c_int64),
+                ("pair_tests", ctypes.c_int64), ("fp64_confirms", ctypes.c_int64),
+                ("brute_chunks", ctypes.c_int64), ("candidates", ctypes.c_int64)]
+
+
+class BTreeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libbtree (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libbtree.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I64 = ctypes.c_int64
+        L.btree_params_default.restype = ctypes.c_int
+        L.btree_params_default.argtypes = [ctypes.POINTER(Params)]
+        L.btree_build.restype = ctypes.c_int
+        L.btree_build.argtypes = [P, P, P, I64, ctypes.POINTER(Params), P, ctypes.POINTER(P)]
+        L.btree_find_neighbors.restype = ctypes.c_int
+        L.btree_find_neighbors.argtypes = [P, P, P, P, P, I64, ctypes.POINTER(I64), P]
+        L.btree_stats.restype = ctypes.c_int
+        L.btree_stats.argtypes = [P, ctypes.POINTER(Stats)]
+        L.btree_export.restype = ctypes.c_int
+        L.btree_export.argtypes = [P, P, P, P, P, P]
+        L.btree_destroy.restype = ctypes.c_int
+        L.btree_destroy.argtypes = [P]
+        L.btree_last_error.restype = ctypes.c_char_p
+        L.btree_last_error.argtypes = []
+        _lib = L
+    return _lib
+
+
+def last_error() -> str:
+    return lib().btree_last_error().decode()
+
+
+def _check(status):
+    if status != BTREE_OK:
+        raise BTreeError(status, last_error())
+
+
+def params(bucket_size=64, alpha=0.5, beta=0.5, max_depth=32, precision="fp32",
+           group_size=0) -> Params:
+    p = Params()
+    _check(lib().btree_params_default(ctypes.byref(p)))
+    p.bucket_size = int(bucket_size)
+    p.alpha = float(alpha)
+    p.beta = float(beta)
+    p.max_depth = int(max_depth)
+    if precision in ("fp32", "fp32_filter", BTREE_FP32_FILTER):
+        p.precision = BTREE_FP32_FILTER
+    elif precision in ("fp64", BTREE_FP64):
+        p.precision = BTREE_FP64
+    else:
+        raise ValueError("precision must be 'fp32' or 'fp64'")
+    p.group_size = int(group_size)
+    return p
+
+
+def _stream(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(a, name):
+    import torch
+    if not isinstance(a, torch.Tensor) or not a.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) torch tensor" % name)
+    if a.dtype != torch.float64:
+        raise TypeError("%s must be float64" % name)
+    if a.dim() != 1 or not a.is_contiguous():
+        raise ValueError("%s must be a contiguous 1-D tensor" % name)
+    return a
+
+
+class BTree:
+    """A b-tree built on the GPU (btree_build) over FP64 coordinates."""
+
+    def __init__(self, x, y, z, bucket_size=64, alpha=0.5, beta=0.5, max_depth=32,
+                 precision="fp32", stream=None):
+        x = _dev_f64(x, "x")
+        y = _dev_f64(y, "y")
+        z = _dev_f64(z, "z")
+        if not (x.shape == y.shape == z.shape):
+            raise ValueError("x, y, z must have the same length")
+        self.n = int(x.shape[0])
+        self.device = x.device
+        self._keep = (x, y, z)
+        p = params(bucket_size, alpha, beta, max_depth, precision)
+        h = ctypes.c_void_p()
+        _check(lib().btree_build(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                 ctypes.c_void_p(z.data_ptr()), self.n, ctypes.byref(p),
+                                 _stream(stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().btree_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def count(self, h, counts=None, offsets=None, stream=None):
+        """Pass 1: (counts int32[n], offsets int64[n+1], total)."""
+        import torch
+        h = _dev_f64(h, "h")
+        if h.shape[0] != self.n:
+            raise ValueError("h must have n entries")
+        if counts is None:
+            counts = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        if offsets is None:
+            offsets = torch.empty(self.n + 1, dtype=torch.int64, device=self.device)
+        total = ctypes.c_int64()
+        _check(lib().btree_find_neighbors(self._h, ctypes.c_void_p(h.data_ptr()),
+                                          ctypes.c_void_p(counts.data_ptr()),
+                                          ctypes.c_void_p(offsets.data_ptr()), None, 0,
+                                          ctypes.byref(total), _stream(stream)))
+        return counts, offsets, int(total.value)
+
+    def fill(self, h, counts, offsets, nbrs, stream=None):
+        """Pass 2 into a caller buffer nbrs (int32, >= total entries)."""
+        total = ctypes.c_int64()
+        _check(lib().btree_find_neighbors(self._h, ctypes.c_void_p(h.data_ptr()),
+                                          ctypes.c_void_p(counts.data_ptr()),
+                                          ctypes.c_void_p(offsets.data_ptr()),
+                                          ctypes.c_void_p(nbrs.data_ptr()), int(nbrs.numel()),
+                                          ctypes.byref(total), _stream(stream)))
+        return int(total.value)
+
+    def find(self, h, stream=None):
+        """FindNeighbors: (counts, offsets, nbrs) as device tensors; row i is
+        nbrs[offsets[i]:offsets[i+1]], ascending original indices."""
+        import torch
+        counts, offsets, total = self.count(h, stream=stream)
+        nbrs = torch.empty(max(total, 1), dtype=torch.int32, device=self.device)
+        self.fill(h, counts, offsets, nbrs, stream=stream)
+        return counts, offsets, nbrs[:total]
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().btree_stats(self._h, ctypes.byref(s)))
+        d = {k: getattr(s, k) for k, _ in Stats._fields_ if k != "b_hist"}
+        d["b_hist"] = {b: int(c) for b, c in enumerate(s.b_hist) if c}
+        return d
+
+    def export(self, stream=None) -> dict:
+        """Leaf layout (memory order) and tree order of the particles (host)."""
+        st = self.stats()
+        nl = st["n_leaves"]
+        beg = np.zeros(max(nl, 1), dtype=np.int32)
+        cnt = np.zeros(max(nl, 1), dtype=np.int32)
+        dep = np.zeros(max(nl, 1), dtype=np.int32)
+        order = np.zeros(max(self.n, 1), dtype=np.int32)
+        _check(lib().btree_export(self._h, beg.ctypes.data, cnt.ctypes.data, dep.ctypes.data,
+                                  order.ctypes.data, _stream(stream)))
+        return {"leaf_beg": beg[:nl], "leaf_cnt": cnt[:nl], "leaf_depth": dep[:nl],
+                "order": order[:self.n]}
+
+
+def find_neighbors(x, y, z, h, bucket_size=64, alpha=0.5, beta=0.5, max_depth=32,
+                   precision="fp32", stream=None):
+    """BuildTree + FindNeighbors in one call; returns (counts, offsets, nbrs)."""
+    with BTree(x, y, z, bucket_size, alpha, beta, max_depth, precision, stream) as t:
+        return t.find(h, stream=stream)

@@ -1,0 +1,213 @@
+// C ABI of libbtree: argument checks, handle lifetime, status codes.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace bt {
+
+static thread_local std::string g_err;
+
+void set_error(const std::string& msg) { g_err = msg; }
+const char* get_error() { return g_err.c_str(); }
+
+static void check_params(const btree_params& p) {
+    if (p.bucket_size < 1) fail(BTREE_EINVAL, "bucket_size must be >= 1");
+    if (!std::isfinite(p.alpha) || p.alpha < 0.0) fail(BTREE_EINVAL, "alpha must be finite and >= 0");
+    if (!std::isfinite(p.beta)) fail(BTREE_EINVAL, "beta must be finite");
+    if (p.max_depth < 0 || p.max_depth > 64) fail(BTREE_EINVAL, "max_depth must be in [0, 64]");
+    if (p.precision != BTREE_FP64 && p.precision != BTREE_FP32_FILTER)
+        fail(BTREE_EINVAL, "precision must be BTREE_FP64 or BTREE_FP32_FILTER");
+    if (p.group_size != 0 && p.group_size != kGroup) fail(BTREE_EINVAL, "group_size must be 0 or 64");
+    for (int k = 0; k < 6; ++k)
+        if (p.reserved[k] != 0) fail(BTREE_EINVAL, "reserved fields must be zero");
+}
+
+template <class F>
+static btree_status guarded(F&& f) {
+    try {
+        f();
+        return BTREE_OK;
+    } catch (const Fail& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return BTREE_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return BTREE_EDEVICE;
+    }
+}
+
+}  // namespace bt
+
+// The opaque handle of the ABI wraps the tree.
+struct btree_tree {
+    bt::Tree t;
+};
+
+using namespace bt;
+
+extern "C" {
+
+btree_status btree_params_default(btree_params* p) {
+    if (!p) {
+        set_error("btree_params_default: NULL");
+        return BTREE_EINVAL;
+    }
+    std::memset(p, 0, sizeof *p);
+    p->bucket_size = 64;
+    p->alpha = 0.5;
+    p->beta = 0.5;
+    p->max_depth = 32;
+    p->precision = BTREE_FP32_FILTER;
+    p->group_size = 0;
+    set_error("");
+    return BTREE_OK;
+}
+
+btree_status btree_build(const double* x, const double* y, const double* z, int64_t n,
+                         const btree_params* p, void* hip_stream, btree_handle* out) {
+    return guarded([&] {
+        if (!out) fail(BTREE_EINVAL, "btree_build: out is NULL");
+        *out = nullptr;
+        if (n < 0 || n >= 0x7fffffffll) fail(BTREE_EINVAL, "btree_build: n must be in [0, 2^31-1)");
+        if (n > 0 && (!x || !y || !z)) fail(BTREE_EINVAL, "btree_build: NULL coordinate array");
+        btree_params prm;
+        if (p) prm = *p;
+        else btree_params_default(&prm);
+        check_params(prm);
+        if ((n + prm.bucket_size - 1) / prm.bucket_size > (1ll << 30))
+            fail(BTREE_EINVAL, "btree_build: n / bucket_size must not exceed 2^30");
+        btree_tree* H = new btree_tree();
+        Tree* t = &H->t;
+        t->n = n;
+        t->prm = prm;
+        if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        try {
+            t->stats.reserve(sizeof(Stats));
+            t->flag.reserve(sizeof(int32_t) * 4);
+            if (n > 0) {
+                build_tree(*t, x, y, z, st);
+            } else {
+                BT_HIP(hipMemsetAsync(t->stats.p, 0, sizeof(Stats), st));
+                BT_HIP(hipStreamSynchronize(st));
+            }
+        } catch (...) {
+            (void)hipStreamSynchronize(st);
+            delete H;
+            throw;
+        }
+        *out = H;
+        set_error("");
+    });
+}
+
+btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* counts,
+                                  int64_t* offsets, int32_t* nbrs, int64_t capacity,
+                                  int64_t* total, void* hip_stream) {
+    return guarded([&] {
+        if (!H) fail(BTREE_ESTATE, "btree_find_neighbors: NULL handle");
+        Tree* t = &H->t;
+        if (!total) fail(BTREE_EINVAL, "btree_find_neighbors: total is NULL");
+        if (!offsets) fail(BTREE_EINVAL, "btree_find_neighbors: offsets is NULL");
+        if (t->n > 0 && (!h || !counts)) fail(BTREE_EINVAL, "btree_find_neighbors: NULL h or counts");
+        if (capacity < 0) fail(BTREE_EINVAL, "btree_find_neighbors: capacity < 0");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        if (t->n == 0) {
+            BT_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), st));
+            BT_HIP(hipStreamSynchronize(st));
+            *total = 0;
+            t->last_total = 0;
+            set_error("");
+            return;
+        }
+        const bool have_pass1 = t->p1_total >= 0 && t->p1_h == h && t->p1_counts == counts &&
+                                t->p1_offsets == offsets;
+        if (nbrs == nullptr || !have_pass1) {
+            t->p1_total = -1;
+            int64_t tot = find_pass1(*t, h, counts, offsets, st);
+            t->p1_h = h;
+            t->p1_counts = counts;
+            t->p1_offsets = offsets;
+            t->p1_total = tot;
+            t->last_total = tot;
+        }
+        *total = t->p1_total;
+        if (nbrs != nullptr) {
+            if (capacity < t->p1_total)
+                fail(BTREE_EOVERFLOW, "btree_find_neighbors: capacity " + std::to_string(capacity) +
+                                          " < total " + std::to_string(t->p1_total));
+            find_pass2(*t, h, offsets, nbrs, st);
+        }
+        set_error("");
+    });
+}
+
+btree_status btree_stats(btree_handle H, btree_stats_t* out) {
+    if (!H || !out) {
+        set_error("btree_stats: NULL argument");
+        return BTREE_EINVAL;
+    }
+    const Tree* t = &H->t;
+    std::memset(out, 0, sizeof *out);
+    out->n = t->n;
+    out->n_internal = t->n_internal;
+    out->n_leaves = t->n_leaves;
+    out->depth = t->depth;
+    out->rounds = (int64_t)t->host_stats.rounds;
+    out->max_leaf = t->max_leaf;
+    out->oversized = t->oversized;
+    out->n_chunks = t->n_chunks;
+    for (int k = 0; k < 65; ++k) out->b_hist[k] = (int64_t)t->host_stats.b_hist[k];
+    out->total = t->last_total;
+    out->pair_tests = (int64_t)t->host_stats.pair_tests;
+    out->fp64_confirms = (int64_t)t->host_stats.confirms;
+    out->brute_chunks = (int64_t)t->host_stats.brute;
+    out->candidates = (int64_t)t->host_stats.candidates;
+    set_error("");
+    return BTREE_OK;
+}
+
+btree_status btree_export(btree_handle H, int32_t* leaf_beg, int32_t* leaf_cnt,
+                          int32_t* leaf_depth, int32_t* order, void* hip_stream) {
+    return guarded([&] {
+        if (!H) fail(BTREE_EINVAL, "btree_export: NULL handle");
+        Tree* t = &H->t;
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        const int64_t nl = t->n_leaves, n = t->n;
+        if (n == 0) return;
+        std::vector<Leaf> L((size_t)nl);
+        if (leaf_beg || leaf_cnt)
+            BT_HIP(hipMemcpyAsync(L.data(), t->leaves.p, sizeof(Leaf) * nl, hipMemcpyDeviceToHost, st));
+        if (leaf_depth)
+            BT_HIP(hipMemcpyAsync(leaf_depth, t->ldepth.p, sizeof(int32_t) * nl,
+                                  hipMemcpyDeviceToHost, st));
+        std::vector<double> P;
+        if (order) {
+            P.resize((size_t)n * 4);
+            BT_HIP(hipMemcpyAsync(P.data(), t->pos.p, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, st));
+        }
+        BT_HIP(hipStreamSynchronize(st));
+        for (int64_t l = 0; l < nl; ++l) {
+            if (leaf_beg) leaf_beg[l] = L[l].beg;
+            if (leaf_cnt) leaf_cnt[l] = L[l].cnt;
+        }
+        if (order)
+            for (int64_t i = 0; i < n; ++i) order[i] = (int32_t)P[(size_t)i * 4 + 3];
+        set_error("");
+    });
+}
+
+btree_status btree_destroy(btree_handle H) {
+    if (!H) return BTREE_OK;
+    (void)hipDeviceSynchronize();
+    delete H;
+    return BTREE_OK;
+}
+
+const char* btree_last_error(void) { return get_error(); }
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// Wavefront and workgroup primitives for gfx950 (wave64).
+#pragma once
+
+#include "common.h"
+
+namespace bt {
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// Number of set bits of `mask` below this lane (v_mbcnt_lo/hi).
+__device__ __forceinline__ int lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <class T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        T t = __shfl_up(v, d, 64);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+template <class T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v += __shfl_xor(v, d, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmin(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Exclusive scan over a workgroup of NT threads (NT multiple of 64).
+// `scratch` must hold NT/64 + 1 int64 values in LDS.  Returns the exclusive
+// prefix of v; *total receives the workgroup sum.  Contains barriers.
+template <int NT>
+__device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t* scratch, int64_t* total) {
+    constexpr int NW = NT / 64;
+    const int w = threadIdx.x >> 6;
+    int64_t inc = wave_incl_scan(v);
+    if (lane_id() == 63) scratch[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int k = 0; k < NW; ++k) {
+            int64_t c = scratch[k];
+            scratch[k] = run;
+            run += c;
+        }
+        scratch[NW] = run;
+    }
+    __syncthreads();
+    int64_t ex = inc - v + scratch[w];
+    *total = scratch[NW];
+    __syncthreads();
+    return ex;
+}
+
+template <int NT>
+__device__ __forceinline__ int64_t block_sum(int64_t v, int64_t* scratch) {
+    constexpr int NW = NT / 64;
+    v = wave_sum(v);
+    if (lane_id() == 0) scratch[threadIdx.x >> 6] = v;
+    __syncthreads();
+    int64_t s = 0;
+    for (int k = 0; k < NW; ++k) s += scratch[k];
+    __syncthreads();
+    return s;
+}
+
+}  // namespace bt

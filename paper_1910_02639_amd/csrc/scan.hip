@@ -1,0 +1,99 @@
+// Exclusive prefix sums into int64 (CSR offsets, node and leaf numbering).
+// Three launches: per-tile sums, one workgroup scanning the tile sums, then
+// per-tile scans that add the tile's base.  out has n+1 entries; out[n] is
+// the total.
+#include "prim.h"
+
+namespace bt {
+
+namespace {
+
+constexpr int kT = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kT * kItems;
+
+template <class In>
+__global__ __launch_bounds__(kT) void k_tile_sum(const In* __restrict__ in, int64_t n,
+                                                 int64_t* __restrict__ tsum) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t k = base + i * kT + threadIdx.x;
+        if (k < n) s += (int64_t)in[k];
+    }
+    s = block_sum<kT>(s, sh);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kT) void k_scan_tiles(int64_t* __restrict__ tsum, int64_t ntiles) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < ntiles; b0 += kT) {
+        int64_t k = b0 + threadIdx.x;
+        int64_t v = k < ntiles ? tsum[k] : 0;
+        int64_t tot;
+        int64_t ex = block_excl_scan<kT>(v, sh, &tot);
+        if (k < ntiles) tsum[k] = carry + ex;
+        carry += tot;
+    }
+    if (threadIdx.x == 0) tsum[ntiles] = carry;
+}
+
+template <class In>
+__global__ __launch_bounds__(kT) void k_tile_scan(const In* __restrict__ in, int64_t n,
+                                                  const int64_t* __restrict__ tsum,
+                                                  int64_t ntiles, int64_t* __restrict__ out,
+                                                  const int* __restrict__ guard) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    if (guard && *guard) return;  // invalid input detected upstream: write nothing
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    int64_t v[kItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t k = base + i;
+        v[i] = k < n ? (int64_t)in[k] : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t ex = block_excl_scan<kT>(s, sh, &tot) + tsum[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t k = base + i;
+        if (k < n) out[k] = ex;
+        ex += v[i];
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tsum[ntiles];
+}
+
+template <class In>
+void scan_impl(const In* in, int64_t* out, int64_t n, Tree& t, hipStream_t st,
+               const int* guard) {
+    int64_t ntiles = (n + kTile - 1) / kTile;
+    if (ntiles < 1) ntiles = 1;
+    t.scan_tmp.reserve(sizeof(int64_t) * (size_t)(ntiles + 1));
+    int64_t* ts = t.scan_tmp.as<int64_t>();
+    hipLaunchKernelGGL(k_tile_sum<In>, dim3((unsigned)ntiles), dim3(kT), 0, st, in, n, ts);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kT), 0, st, ts, ntiles);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_tile_scan<In>, dim3((unsigned)ntiles), dim3(kT), 0, st, in, n, ts,
+                       ntiles, out, guard);
+    BT_LAUNCH();
+}
+
+}  // namespace
+
+void scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, Tree& t, hipStream_t st,
+                        const int* guard) {
+    scan_impl<int32_t>(in, out, n, t, st, guard);
+}
+
+void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, Tree& t, hipStream_t st,
+                        const int* guard) {
+    scan_impl<int64_t>(in, out, n, t, st, guard);
+}
+
+}  // namespace bt

@@ -1,0 +1,58 @@
+"""Shared helpers of the GPU parity tests (no method arithmetic here)."""
+import sys
+import time
+
+import numpy as np
+
+
+def log(*a):
+    print("[%s]" % time.strftime("%H:%M:%S"), *a, file=sys.stderr, flush=True)
+
+
+def to_dev(*arrays):
+    import torch
+    return [torch.from_numpy(np.ascontiguousarray(a, dtype=np.float64)).to("cuda:0")
+            for a in arrays]
+
+
+def gpu_lists(x, y, z, h, precision="fp32", bucket_size=64, alpha=0.5, beta=0.5,
+              max_depth=32):
+    """Build + find on cuda:0; returns host (counts int64, offsets, nbrs, stats)."""
+    from paper_1910_02639_amd import btree
+    import torch
+    dx, dy, dz, dh = to_dev(x, y, z, h)
+    with btree.BTree(dx, dy, dz, bucket_size, alpha, beta, max_depth, precision) as t:
+        c, o, nb = t.find(dh)
+        torch.cuda.synchronize()
+        st = t.stats()
+    return (c.cpu().numpy().astype(np.int64), o.cpu().numpy(), nb.cpu().numpy(), st)
+
+
+def assert_same_lists(got, want, rows=None):
+    """Element-by-element equality of CSR lists (got from the GPU, want from
+    the oracle restricted to `rows` when given)."""
+    gc, go, gn = got[:3]
+    wc, wo, wn = want
+    if rows is None:
+        assert np.array_equal(gc, wc), "counts differ at %s" % np.nonzero(gc != wc)[0][:10]
+        assert np.array_equal(go, wo), "offsets differ"
+        assert np.array_equal(gn, wn), "lists differ"
+        return
+    for k, i in enumerate(rows):
+        a = gn[go[i]:go[i + 1]]
+        b = wn[wo[k]:wo[k + 1]]
+        assert gc[i] == wc[k], (i, gc[i], wc[k])
+        assert np.array_equal(a, b), "row %d differs" % i
+
+
+def check_csr_invariants(counts, offsets, nbrs, n):
+    assert offsets[0] == 0
+    assert np.array_equal(np.diff(offsets), counts)
+    assert offsets[-1] == nbrs.shape[0]
+    if nbrs.shape[0]:
+        assert nbrs.min() >= 0 and nbrs.max() < n
+    # rows strictly ascending: any non-increase must sit at a row boundary
+    if nbrs.shape[0] > 1:
+        bad = np.nonzero(np.diff(nbrs.astype(np.int64)) <= 0)[0] + 1
+        starts = set(offsets[:-1].tolist())
+        assert all(int(b) in starts for b in bad)

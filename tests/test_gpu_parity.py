@@ -1,0 +1,255 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Neighbour counts and lists are integers and must be equal element by
+element, for both arithmetic forms (FP64 and FP32 filter + FP64 band).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1910_02639_amd import workloads as W
+from tests.helpers import (assert_same_lists, check_csr_invariants, gpu_lists, log, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+PRECS = ["fp32", "fp64"]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    oracle.build(force=False)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_uniform_10k_full(prec, seed):
+    x, y, z, h = W.uniform_cube(10_000, seed, 64.0)
+    log("U10k seed", seed, prec)
+    got = gpu_lists(x, y, z, h, prec, bucket_size=64)
+    want = oracle.lists(x, y, z, h)
+    assert_same_lists(got, want)
+    st = got[3]
+    assert st["brute_chunks"] == 0
+    assert st["total"] == want[0].sum()
+
+
+@pytest.mark.parametrize("prec", PRECS)
+@pytest.mark.parametrize("n,s", [(1, 64), (2, 1), (63, 64), (64, 64), (65, 64), (300, 8),
+                                 (2000, 16), (5000, 128), (4097, 32)])
+def test_small_random_full(prec, n, s):
+    rng = np.random.default_rng(1000 + n + s)
+    x, y, z = rng.normal(size=(3, n))
+    h = rng.uniform(0.05, 0.4, n)
+    h[::7] = 0.0  # some empty rows
+    log("small", n, s, prec)
+    got = gpu_lists(x, y, z, h, prec, bucket_size=s)
+    want = oracle.lists(x, y, z, h)
+    assert_same_lists(got, want)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_plummer_small_full(prec):
+    x, y, z, h = W.plummer(30_000, 5)
+    log("plummer 30k", prec)
+    got = gpu_lists(x, y, z, h, prec, bucket_size=32)
+    want = oracle.lists(x, y, z, h)
+    assert_same_lists(got, want)
+    assert got[3]["brute_chunks"] == 0
+
+
+@pytest.mark.parametrize("name,s,kw", [("U10k", 64, {}), ("P60k", 32, {}),
+                                       ("P60k", 16, {"beta": 0.2}), ("L1M", 128, {})])
+def test_tree_matches_algorithm1(name, s, kw):
+    """Integer tree shape (leaf sizes, depths, members, b per cell) equals the
+    oracle's recursive Algorithm 1, leaf by leaf in depth-first order."""
+    from paper_1910_02639_amd import btree
+    if name == "U10k":
+        x, y, z, _ = W.uniform_cube(10_000, 0)
+    elif name == "P60k":
+        x, y, z, _ = W.plummer(60_000, 2)
+    else:
+        x, y, z, _ = W.lattice()
+    log("tree", name, s, kw)
+    ref = oracle.build_tree(x, y, z, s=s, **kw)
+    dx, dy, dz = to_dev(x, y, z)
+    with btree.BTree(dx, dy, dz, bucket_size=s, **kw) as t:
+        st = t.stats()
+        ex = t.export()
+    assert st["n_leaves"] == ref.n_leaves
+    assert st["n_internal"] == ref.n_internal
+    assert st["depth"] == ref.depth
+    assert st["rounds"] == ref.rounds
+    assert st["b_hist"] == {b if b < 64 else 64: c for b, c in ref.b_hist.items()}
+    assert np.array_equal(ex["leaf_cnt"], ref.leaf_cnt)
+    assert np.array_equal(ex["leaf_depth"], ref.leaf_depth)
+    off = ref.leaf_offsets()
+    assert np.array_equal(ex["leaf_beg"], off[:-1])
+    order = ex["order"]
+    for l in range(ref.n_leaves):
+        a = np.sort(order[off[l]:off[l + 1]])
+        assert np.array_equal(a, ref.members[off[l]:off[l + 1]]), l
+
+
+def _lattice_expected_counts(m=100):
+    i = np.arange(m ** 3, dtype=np.int64)
+    ix, iy, iz = i // (m * m), (i // m) % m, i % m
+    cnt = np.zeros(m ** 3, dtype=np.int64)
+    for a in range(-2, 3):
+        for b in range(-2, 3):
+            for c in range(-2, 3):
+                if a * a + b * b + c * c <= 8:
+                    ok = ((ix + a >= 0) & (ix + a < m) & (iy + b >= 0) & (iy + b < m) &
+                          (iz + c >= 0) & (iz + c < m))
+                    cnt += ok
+    return cnt
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_lattice_1m(prec):
+    x, y, z, h = W.lattice()
+    log("L1M", prec)
+    c, o, nb, st = gpu_lists(x, y, z, h, prec, bucket_size=128)
+    check_csr_invariants(c, o, nb, len(x))
+    assert o[-1] == 90_205_144
+    assert np.array_equal(c, _lattice_expected_counts())
+    assert st["depth"] == 1 and st["n_leaves"] == 8000 and st["b_hist"] == {20: 1}
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([[0, 1, 99, 10_000, 999_999, 505_050],
+                                     rng.integers(0, len(x), 200)]))
+    want = oracle.lists(x, y, z, h, rows)
+    assert_same_lists((c, o, nb), want, rows)
+    # constant h: lists are symmetric
+    r = np.repeat(np.arange(len(x), dtype=np.int64), c)
+    fwd = r * len(x) + nb
+    bwd = nb.astype(np.int64) * len(x) + r
+    assert np.array_equal(np.sort(fwd), np.sort(bwd))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_plummer_8m_sampled(prec):
+    x, y, z, h = W.plummer(8_000_000, 0)
+    log("P8M", prec)
+    c, o, nb, st = gpu_lists(x, y, z, h, prec, bucket_size=128)
+    log("P8M total", int(o[-1]), st)
+    check_csr_invariants(c, o, nb, len(x))
+    r = np.sqrt(x * x + y * y + z * z)
+    rng = np.random.default_rng(3)
+    core = np.argsort(r)[:20]
+    edge = np.argsort(r)[-20:]
+    rows = np.unique(np.concatenate([core, edge, rng.integers(0, len(x), 260)]))
+    want = oracle.lists(x, y, z, h, rows)
+    assert_same_lists((c, o, nb), want, rows)
+    assert st["brute_chunks"] == 0
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_edge_cases(prec):
+    rng = np.random.default_rng(17)
+    # coincident particles beyond the bucket size (depth guard), plus others
+    x = np.concatenate([np.full(300, 0.25), rng.random(700)])
+    y = np.concatenate([np.full(300, 0.5), rng.random(700)])
+    z = np.concatenate([np.full(300, 0.75), rng.random(700)])
+    h = np.full(1000, 0.02)
+    got = gpu_lists(x, y, z, h, prec, bucket_size=16, max_depth=12)
+    assert_same_lists(got, oracle.lists(x, y, z, h))
+    assert got[3]["oversized"] >= 1
+    # a plane (zero extent along z) and a line
+    x, y = rng.random((2, 3000))
+    z = np.zeros(3000)
+    h = np.full(3000, 0.03)
+    assert_same_lists(gpu_lists(x, y, z, h, prec, bucket_size=32),
+                      oracle.lists(x, y, z, h))
+    y = np.zeros(3000)
+    assert_same_lists(gpu_lists(x, y, z, h, prec, bucket_size=32),
+                      oracle.lists(x, y, z, h))
+    # far from the origin, negative coordinates
+    x, y, z, h = W.uniform_cube(5000, 3, 64.0)
+    x = x * 1e-3 - 1e6
+    y = y * 1e-3 + 3e5
+    z = z * 1e-3
+    h = h * 1e-3
+    assert_same_lists(gpu_lists(x, y, z, h, prec), oracle.lists(x, y, z, h))
+    # all zero h: every row empty
+    x, y, z, h = W.uniform_cube(3000, 4, 64.0)
+    got = gpu_lists(x, y, z, np.zeros(3000), prec)
+    assert got[0].sum() == 0
+    # radius above the diagonal: every row is 0..n-1 (exhaustive path)
+    got = gpu_lists(x[:2500], y[:2500], z[:2500], np.full(2500, 5.0), prec)
+    assert np.all(got[0] == 2500)
+    assert np.array_equal(got[2].reshape(2500, 2500), np.tile(np.arange(2500), (2500, 1)))
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_band_pairs_exact(prec):
+    """Pairs placed on, just inside and just outside 2h_i (relative steps of
+    a few FP32 ulps) go through the FP64 confirmation and still match."""
+    rng = np.random.default_rng(23)
+    n0 = 400
+    cx, cy, cz = rng.random((3, n0)) * 10.0
+    hq = rng.uniform(0.01, 0.1, n0)
+    xs, ys, zs, hs = [cx], [cy], [cz], [hq]
+    for k in (-3, -1, 0, 1, 3):
+        d = rng.normal(size=(3, n0))
+        d /= np.linalg.norm(d, axis=0)
+        R = 2.0 * hq * (1.0 + k * 2.0 ** -24)
+        xs.append(cx + R * d[0]); ys.append(cy + R * d[1]); zs.append(cz + R * d[2])
+        hs.append(np.full(n0, 0.001))
+    # exact ties along an axis: x_j = x_i + 2h_i with representable values
+    tx = np.arange(n0, dtype=np.float64) * 4.0
+    xs.append(tx); ys.append(np.full(n0, 50.0)); zs.append(np.zeros(n0)); hs.append(np.full(n0, 0.5))
+    xs.append(tx + 1.0); ys.append(np.full(n0, 50.0)); zs.append(np.zeros(n0)); hs.append(np.full(n0, 0.25))
+    x, y, z, h = (np.concatenate(v) for v in (xs, ys, zs, hs))
+    got = gpu_lists(x, y, z, h, prec, bucket_size=32)
+    assert_same_lists(got, oracle.lists(x, y, z, h))
+    if prec == "fp32":
+        assert got[3]["fp64_confirms"] > 0
+
+
+def test_empty_and_invalid():
+    import torch
+    from paper_1910_02639_amd import btree
+    e = torch.empty(0, dtype=torch.float64, device="cuda:0")
+    with btree.BTree(e, e, e) as t:
+        c, o, nb = t.find(e)
+        assert o.cpu().tolist() == [0] and nb.numel() == 0
+    x, y, z, h = W.uniform_cube(2000, 5, 64.0)
+    dx, dy, dz, dh = to_dev(x, y, z, h)
+    bad = dh.clone()
+    bad[17] = float("nan")
+    with btree.BTree(dx, dy, dz) as t:
+        counts = torch.full((2000,), -7, dtype=torch.int32, device="cuda:0")
+        offs = torch.full((2001,), -7, dtype=torch.int64, device="cuda:0")
+        with pytest.raises(btree.BTreeError) as ei:
+            t.count(bad, counts, offs)
+        assert ei.value.status == btree.BTREE_EINVAL
+        assert int((counts != -7).sum()) == 0 and int((offs != -7).sum()) == 0
+        neg = dh.clone()
+        neg[3] = -1.0
+        with pytest.raises(btree.BTreeError):
+            t.count(neg)
+        # a valid call still works after the failures
+        c, o, tot = t.count(dh)
+        small = torch.empty(max(tot - 1, 0), dtype=torch.int32, device="cuda:0")
+        with pytest.raises(btree.BTreeError) as ei:
+            t.fill(dh, c, o, small)
+        assert ei.value.status == btree.BTREE_EOVERFLOW
+    xb = dx.clone()
+    xb[5] = float("inf")
+    with pytest.raises(btree.BTreeError) as ei:
+        btree.BTree(xb, dy, dz)
+    assert ei.value.status == btree.BTREE_EINVAL
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_deterministic(prec):
+    x, y, z, h = W.plummer(200_000, 8)
+    a = gpu_lists(x, y, z, h, prec, bucket_size=64)
+    b = gpu_lists(x, y, z, h, prec, bucket_size=64)
+    for u, v in zip(a[:3], b[:3]):
+        assert np.array_equal(u, v)
+    # parameter independence of the result
+    c = gpu_lists(x, y, z, h, "fp64" if prec == "fp32" else "fp32", bucket_size=16, beta=0.3)
+    for u, v in zip(a[:3], c[:3]):
+        assert np.array_equal(u, v)
