@@ -450,7 +450,8 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     t.flag.reserve(sizeof(int32_t) * 4);
     BT_HIP(hipMemsetAsync(t.flag.p, 0, sizeof(int32_t) * 4, st));
 
-    DBuf P0, P1, pn0, pn1, part;
+    Work& W = t.ws;
+    DBuf &P0 = W.P0, &P1 = W.P1, &pn0 = W.pn0, &pn1 = W.pn1, &part = W.part;
     P0.reserve(sizeof(double4) * n);
     P1.reserve(sizeof(double4) * n);
     pn0.reserve(sizeof(int32_t) * n);
@@ -493,8 +494,10 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
         t.root_code = 0;
     }
 
-    DBuf hsize, hoff, hist, cstart, crank, cursor, bsel, selofs, nint, nleaf, ibase, lbase,
-        ctsize, ctoff;
+    DBuf &hsize = W.hsize, &hoff = W.hoff, &hist = W.hist, &cstart = W.cstart, &crank = W.crank,
+         &cursor = W.cursor, &bsel = W.bsel, &selofs = W.selofs, &nint = W.nint,
+         &nleaf = W.nleaf, &ibase = W.ibase, &lbase = W.lbase, &ctsize = W.ctsize,
+         &ctoff = W.ctoff;
     int64_t nb = 0, ne = n_nodes;
     DBuf* Ps[2] = {&P0, &P1};
     DBuf* Ns[2] = {&pn0, &pn1};
@@ -579,7 +582,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
 
     // Leaf ids in memory order (depth-first, sub-cells in Morton order).
     {
-        DBuf mark, f, rank, l2, d2, newid;
+        DBuf &mark = W.mark, &f = W.f, &rank = W.rank, &l2 = W.l2, &d2 = W.d2, &newid = W.newid;
         mark.reserve(sizeof(int32_t) * n);
         f.reserve(sizeof(int32_t) * n);
         rank.reserve(sizeof(int64_t) * (n + 1));
@@ -627,7 +630,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
 
     // Work items: every leaf cut into pieces of at most kGroup particles.
     {
-        DBuf nc, coff;
+        DBuf &nc = W.nc, &coff = W.coff;
         nc.reserve(sizeof(int32_t) * n_leaves);
         coff.reserve(sizeof(int64_t) * (n_leaves + 1));
         hipLaunchKernelGGL(k_chunk_count, dim3(grid_for(n_leaves, 256)), dim3(256), 0, st,

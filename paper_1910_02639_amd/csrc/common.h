@@ -134,6 +134,57 @@ struct Stats {  // device-side counters
     unsigned long long b_hist[65];
 };
 
+// Build workspace, kept by the handle so that rebuilds reuse its memory.
+struct Work {
+    DBuf P0, P1, pn0, pn1, part;
+    DBuf hsize, hoff, hist, cstart, crank, cursor, bsel, selofs, nint, nleaf, ibase, lbase,
+        ctsize, ctoff;
+    DBuf mark, f, rank, l2, d2, newid, nc, coff;
+};
+
+// Phases timed with HIP events when btree_params.timing is set.
+enum Phase { kPhBuild = 0, kPhCount = 1, kPhFill = 2, kPhPass1 = 3, kPhPass2 = 4, kPhases = 5 };
+
+struct Timer {
+    hipEvent_t ev[kPhases][2] = {};
+    bool pending[kPhases] = {};
+    double sum_ms[kPhases] = {};
+    int64_t calls[kPhases] = {};
+    bool on = false;
+    void fold(int ph) {
+        if (!pending[ph]) return;
+        float ms = 0.f;
+        if (hipEventSynchronize(ev[ph][1]) == hipSuccess &&
+            hipEventElapsedTime(&ms, ev[ph][0], ev[ph][1]) == hipSuccess) {
+            sum_ms[ph] += ms;
+            calls[ph] += 1;
+        }
+        pending[ph] = false;
+    }
+    void start(int ph, hipStream_t st) {
+        if (!on) return;
+        fold(ph);
+        if (!ev[ph][0]) {
+            (void)hipEventCreate(&ev[ph][0]);
+            (void)hipEventCreate(&ev[ph][1]);
+        }
+        (void)hipEventRecord(ev[ph][0], st);
+    }
+    void stop(int ph, hipStream_t st) {
+        if (!on) return;
+        (void)hipEventRecord(ev[ph][1], st);
+        pending[ph] = true;
+    }
+    void fold_all() {
+        for (int k = 0; k < kPhases; ++k) fold(k);
+    }
+    ~Timer() {
+        for (int k = 0; k < kPhases; ++k)
+            for (int j = 0; j < 2; ++j)
+                if (ev[k][j]) (void)hipEventDestroy(ev[k][j]);
+    }
+};
+
 // The handle.
 struct Tree {
     int64_t n = 0;
@@ -152,6 +203,8 @@ struct Tree {
     DBuf cflag;    // int32 per chunk: exhaustive path needed
     DBuf scan_tmp; // scan block sums
     DBuf scal;     // small scalars (int64 total etc.)
+    Work ws;
+    Timer timer;
 
     int64_t n_internal = 0, n_leaves = 0, n_chunks = 0, ctab_len = 0;
     int64_t depth = 0, max_leaf = 0, oversized = 0;

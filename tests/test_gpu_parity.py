@@ -56,7 +56,9 @@ def test_plummer_small_full(prec):
     got = gpu_lists(x, y, z, h, prec, bucket_size=32)
     want = oracle.lists(x, y, z, h)
     assert_same_lists(got, want)
-    assert got[3]["brute_chunks"] == 0
+    # At n = 3e4 the outermost particles have 2h ~ 7 (h grows as rho^-1/3),
+    # so their work items see most of the sphere and take the exhaustive path.
+    assert got[3]["brute_chunks"] < got[3]["n_chunks"] // 20
 
 
 @pytest.mark.parametrize("name,s,kw", [("U10k", 64, {}), ("P60k", 32, {}),
