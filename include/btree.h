@@ -64,7 +64,10 @@ typedef struct {
     int32_t precision;      /* btree_precision; default BTREE_FP32_FILTER     */
     int32_t group_size;     /* queries per wavefront work item, 0 = library
                                choice (64); must be 0 or 64                   */
-    int32_t reserved[6];    /* must be zero                                   */
+    int32_t timing;         /* 1: time each phase with HIP events recorded on
+                               the caller's stream (btree_stats.phase_ms);
+                               default 0                                      */
+    int32_t reserved[5];    /* must be zero                                   */
 } btree_params;
 
 /* Shape of a built tree and counters of the last search. */
@@ -85,6 +88,12 @@ typedef struct {
     int64_t fp64_confirms;  /* FP32-filter pairs re-tested in FP64            */
     int64_t brute_chunks;   /* work items that took the exhaustive path       */
     int64_t candidates;     /* culled candidates staged, summed over items    */
+    /* with params.timing = 1, device time of each phase summed over the
+       calls since btree_build (btree_rebuild keeps counting):
+       [0] build, [1] search count kernel, [2] search fill kernel,
+       [3] whole pass 1, [4] whole pass 2; phase_calls counts the calls.   */
+    double  phase_ms[5];
+    int64_t phase_calls[5];
 } btree_stats_t;
 
 typedef struct btree_tree* btree_handle;
@@ -108,6 +117,13 @@ btree_status btree_build(const double* x, const double* y, const double* z,
                          int64_t n, const btree_params* p, void* hip_stream,
                          btree_handle* out);
 
+/* BuildTree again on the handle `t` over new coordinates (n may differ),
+ * with the handle's parameters, reusing its device memory where it is large
+ * enough.  Same semantics and errors as btree_build; on failure the handle
+ * holds no tree (a search returns BTREE_ESTATE) until a rebuild succeeds. */
+btree_status btree_rebuild(btree_handle t, const double* x, const double* y,
+                           const double* z, int64_t n, void* hip_stream);
+
 /* FindNeighbors (Algorithm 2, Eq. 5) for every particle of the tree.
  * Row i lists, in ascending original index, every j with
  *     ((dx*dx + dy*dy) + dz*dz) < (2*h_i)*(2*h_i),
@@ -129,7 +145,8 @@ btree_status btree_build(const double* x, const double* y, const double* z,
  *   nbrs[0..total) and *total, without synchronising.
  * Otherwise (nbrs != NULL, no matching pass 1): runs both passes.
  * Errors: EINVAL (NULL h/counts/offsets/total with n > 0, bad h values),
- *   EOVERFLOW (capacity < total; nbrs untouched), ESTATE (NULL handle),
+ *   EOVERFLOW (capacity < total; nbrs untouched), ESTATE (NULL handle, or
+ *   a handle whose last rebuild failed),
  *   ENOMEM, EDEVICE. */
 btree_status btree_find_neighbors(btree_handle t, const double* h,
                                   int32_t* counts, int64_t* offsets,

@@ -27,15 +27,15 @@ BTREE_FP32_FILTER = 1
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW",
                 -5: "ESTATE"}
 
-SYMBOLS = ["btree_params_default", "btree_build", "btree_find_neighbors", "btree_stats",
-           "btree_export", "btree_destroy", "btree_last_error"]
+SYMBOLS = ["btree_params_default", "btree_build", "btree_rebuild", "btree_find_neighbors",
+           "btree_stats", "btree_export", "btree_destroy", "btree_last_error"]
 
 
 class Params(ctypes.Structure):
     _fields_ = [("bucket_size", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("max_depth", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("group_size", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 class Stats(ctypes.Structure):
@@ -45,7 +45,10 @@ class Stats(ctypes.Structure):
                 ("oversized", ctypes.c_int64), ("n_chunks", ctypes.c_int64),
                 ("b_hist", ctypes.c_int64 * 65), ("total", ctypes.c_int64),
                 ("pair_tests", ctypes.c_int64), ("fp64_confirms", ctypes.c_int64),
-                ("brute_chunks", ctypes.c_int64), ("candidates", ctypes.c_int64)]
+                ("brute_chunks", ctypes.c_int64), ("candidates", ctypes.c_int64),
+                ("phase_ms", ctypes.c_double * 5), ("phase_calls", ctypes.c_int64 * 5)]
+
+PHASES = ["build", "count_kernel", "fill_kernel", "pass1", "pass2"]
 
 
 class BTreeError(RuntimeError):
@@ -70,6 +73,8 @@ def lib():
         L.btree_params_default.argtypes = [ctypes.POINTER(Params)]
         L.btree_build.restype = ctypes.c_int
         L.btree_build.argtypes = [P, P, P, I64, ctypes.POINTER(Params), P, ctypes.POINTER(P)]
+        L.btree_rebuild.restype = ctypes.c_int
+        L.btree_rebuild.argtypes = [P, P, P, P, I64, P]
         L.btree_find_neighbors.restype = ctypes.c_int
         L.btree_find_neighbors.argtypes = [P, P, P, P, P, I64, ctypes.POINTER(I64), P]
         L.btree_stats.restype = ctypes.c_int
@@ -94,7 +99,7 @@ def _check(status):
 
 
 def params(bucket_size=64, alpha=0.5, beta=0.5, max_depth=32, precision="fp32",
-           group_size=0) -> Params:
+           group_size=0, timing=False) -> Params:
     p = Params()
     _check(lib().btree_params_default(ctypes.byref(p)))
     p.bucket_size = int(bucket_size)
@@ -108,6 +113,7 @@ def params(bucket_size=64, alpha=0.5, beta=0.5, max_depth=32, precision="fp32",
     else:
         raise ValueError("precision must be 'fp32' or 'fp64'")
     p.group_size = int(group_size)
+    p.timing = 1 if timing else 0
     return p
 
 
@@ -132,7 +138,7 @@ class BTree:
     """A b-tree built on the GPU (btree_build) over FP64 coordinates."""
 
     def __init__(self, x, y, z, bucket_size=64, alpha=0.5, beta=0.5, max_depth=32,
-                 precision="fp32", stream=None):
+                 precision="fp32", stream=None, timing=False):
         x = _dev_f64(x, "x")
         y = _dev_f64(y, "y")
         z = _dev_f64(z, "z")
@@ -141,13 +147,25 @@ class BTree:
         self.n = int(x.shape[0])
         self.device = x.device
         self._keep = (x, y, z)
-        p = params(bucket_size, alpha, beta, max_depth, precision)
+        p = params(bucket_size, alpha, beta, max_depth, precision, timing=timing)
         h = ctypes.c_void_p()
         _check(lib().btree_build(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                  ctypes.c_void_p(z.data_ptr()), self.n, ctypes.byref(p),
                                  _stream(stream), ctypes.byref(h)))
         self._h = h
         self._keep = None
+
+    def rebuild(self, x, y, z, stream=None):
+        """BuildTree again over new coordinates, reusing the handle's memory."""
+        x = _dev_f64(x, "x")
+        y = _dev_f64(y, "y")
+        z = _dev_f64(z, "z")
+        if not (x.shape == y.shape == z.shape):
+            raise ValueError("x, y, z must have the same length")
+        self.n = int(x.shape[0])
+        _check(lib().btree_rebuild(self._h, ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                   self.n, _stream(stream)))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -205,8 +223,11 @@ class BTree:
     def stats(self) -> dict:
         s = Stats()
         _check(lib().btree_stats(self._h, ctypes.byref(s)))
-        d = {k: getattr(s, k) for k, _ in Stats._fields_ if k != "b_hist"}
+        d = {k: getattr(s, k) for k, _ in Stats._fields_
+             if k not in ("b_hist", "phase_ms", "phase_calls")}
         d["b_hist"] = {b: int(c) for b, c in enumerate(s.b_hist) if c}
+        d["phase_ms"] = {k: float(s.phase_ms[i]) for i, k in enumerate(PHASES)}
+        d["phase_calls"] = {k: int(s.phase_calls[i]) for i, k in enumerate(PHASES)}
         return d
 
     def export(self, stream=None) -> dict:

@@ -20,7 +20,8 @@ static void check_params(const btree_params& p) {
     if (p.precision != BTREE_FP64 && p.precision != BTREE_FP32_FILTER)
         fail(BTREE_EINVAL, "precision must be BTREE_FP64 or BTREE_FP32_FILTER");
     if (p.group_size != 0 && p.group_size != kGroup) fail(BTREE_EINVAL, "group_size must be 0 or 64");
-    for (int k = 0; k < 6; ++k)
+    if (p.timing != 0 && p.timing != 1) fail(BTREE_EINVAL, "timing must be 0 or 1");
+    for (int k = 0; k < 5; ++k)
         if (p.reserved[k] != 0) fail(BTREE_EINVAL, "reserved fields must be zero");
 }
 
@@ -49,6 +50,44 @@ struct btree_tree {
 
 using namespace bt;
 
+namespace bt {
+
+static void check_n(int64_t n, const double* x, const double* y, const double* z, int32_t s) {
+    if (n < 0 || n >= 0x7fffffffll) fail(BTREE_EINVAL, "n must be in [0, 2^31-1)");
+    if (n > 0 && (!x || !y || !z)) fail(BTREE_EINVAL, "NULL coordinate array");
+    if ((n + s - 1) / s > (1ll << 30)) fail(BTREE_EINVAL, "n / bucket_size must not exceed 2^30");
+}
+
+// (Re)builds the tree of t; the handle keeps its buffers.
+static void do_build(Tree* t, const double* x, const double* y, const double* z, int64_t n,
+                     hipStream_t st) {
+    t->valid = false;
+    t->n = n;
+    t->p1_total = -1;
+    t->p1_h = nullptr;
+    t->p1_counts = nullptr;
+    t->p1_offsets = nullptr;
+    t->last_total = 0;
+    t->n_internal = t->n_leaves = t->n_chunks = t->ctab_len = 0;
+    t->depth = t->max_leaf = t->oversized = 0;
+    t->root_code = kEmpty;
+    t->host_stats = Stats{};
+    t->timer.on = t->prm.timing != 0;
+    t->stats.reserve(sizeof(Stats));
+    t->flag.reserve(sizeof(int32_t) * 4);
+    t->timer.start(kPhBuild, st);
+    if (n > 0) {
+        build_tree(*t, x, y, z, st);
+    } else {
+        BT_HIP(hipMemsetAsync(t->stats.p, 0, sizeof(Stats), st));
+    }
+    t->timer.stop(kPhBuild, st);
+    BT_HIP(hipStreamSynchronize(st));
+    t->valid = true;
+}
+
+}  // namespace bt
+
 extern "C" {
 
 btree_status btree_params_default(btree_params* p) {
@@ -72,29 +111,18 @@ btree_status btree_build(const double* x, const double* y, const double* z, int6
     return guarded([&] {
         if (!out) fail(BTREE_EINVAL, "btree_build: out is NULL");
         *out = nullptr;
-        if (n < 0 || n >= 0x7fffffffll) fail(BTREE_EINVAL, "btree_build: n must be in [0, 2^31-1)");
-        if (n > 0 && (!x || !y || !z)) fail(BTREE_EINVAL, "btree_build: NULL coordinate array");
         btree_params prm;
         if (p) prm = *p;
         else btree_params_default(&prm);
         check_params(prm);
-        if ((n + prm.bucket_size - 1) / prm.bucket_size > (1ll << 30))
-            fail(BTREE_EINVAL, "btree_build: n / bucket_size must not exceed 2^30");
+        check_n(n, x, y, z, prm.bucket_size);
         btree_tree* H = new btree_tree();
         Tree* t = &H->t;
-        t->n = n;
         t->prm = prm;
         if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
         hipStream_t st = static_cast<hipStream_t>(hip_stream);
         try {
-            t->stats.reserve(sizeof(Stats));
-            t->flag.reserve(sizeof(int32_t) * 4);
-            if (n > 0) {
-                build_tree(*t, x, y, z, st);
-            } else {
-                BT_HIP(hipMemsetAsync(t->stats.p, 0, sizeof(Stats), st));
-                BT_HIP(hipStreamSynchronize(st));
-            }
+            do_build(t, x, y, z, n, st);
         } catch (...) {
             (void)hipStreamSynchronize(st);
             delete H;
@@ -105,12 +133,31 @@ btree_status btree_build(const double* x, const double* y, const double* z, int6
     });
 }
 
+btree_status btree_rebuild(btree_handle H, const double* x, const double* y, const double* z,
+                           int64_t n, void* hip_stream) {
+    return guarded([&] {
+        if (!H) fail(BTREE_ESTATE, "btree_rebuild: NULL handle");
+        Tree* t = &H->t;
+        check_n(n, x, y, z, t->prm.bucket_size);
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        try {
+            do_build(t, x, y, z, n, st);
+        } catch (...) {
+            (void)hipStreamSynchronize(st);
+            t->valid = false;
+            throw;
+        }
+        set_error("");
+    });
+}
+
 btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* counts,
                                   int64_t* offsets, int32_t* nbrs, int64_t capacity,
                                   int64_t* total, void* hip_stream) {
     return guarded([&] {
         if (!H) fail(BTREE_ESTATE, "btree_find_neighbors: NULL handle");
         Tree* t = &H->t;
+        if (!t->valid) fail(BTREE_ESTATE, "btree_find_neighbors: the handle holds no tree");
         if (!total) fail(BTREE_EINVAL, "btree_find_neighbors: total is NULL");
         if (!offsets) fail(BTREE_EINVAL, "btree_find_neighbors: offsets is NULL");
         if (t->n > 0 && (!h || !counts)) fail(BTREE_EINVAL, "btree_find_neighbors: NULL h or counts");
@@ -128,7 +175,9 @@ btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* coun
                                 t->p1_offsets == offsets;
         if (nbrs == nullptr || !have_pass1) {
             t->p1_total = -1;
+            t->timer.start(kPhPass1, st);
             int64_t tot = find_pass1(*t, h, counts, offsets, st);
+            t->timer.stop(kPhPass1, st);
             t->p1_h = h;
             t->p1_counts = counts;
             t->p1_offsets = offsets;
@@ -140,7 +189,9 @@ btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* coun
             if (capacity < t->p1_total)
                 fail(BTREE_EOVERFLOW, "btree_find_neighbors: capacity " + std::to_string(capacity) +
                                           " < total " + std::to_string(t->p1_total));
+            t->timer.start(kPhPass2, st);
             find_pass2(*t, h, offsets, nbrs, st);
+            t->timer.stop(kPhPass2, st);
         }
         set_error("");
     });
@@ -151,7 +202,8 @@ btree_status btree_stats(btree_handle H, btree_stats_t* out) {
         set_error("btree_stats: NULL argument");
         return BTREE_EINVAL;
     }
-    const Tree* t = &H->t;
+    Tree* t = &H->t;
+    t->timer.fold_all();
     std::memset(out, 0, sizeof *out);
     out->n = t->n;
     out->n_internal = t->n_internal;
@@ -167,6 +219,10 @@ btree_status btree_stats(btree_handle H, btree_stats_t* out) {
     out->fp64_confirms = (int64_t)t->host_stats.confirms;
     out->brute_chunks = (int64_t)t->host_stats.brute;
     out->candidates = (int64_t)t->host_stats.candidates;
+    for (int k = 0; k < kPhases; ++k) {
+        out->phase_ms[k] = t->timer.sum_ms[k];
+        out->phase_calls[k] = t->timer.calls[k];
+    }
     set_error("");
     return BTREE_OK;
 }

@@ -30,12 +30,12 @@ namespace {
 constexpr int kT = 256;
 constexpr int kIngestBlocks = 1024;
 
+// A1: validate coordinates, keep an original-order copy, bounding-box
+// partials per block.
 __global__ __launch_bounds__(kT) void k_ingest(const double* __restrict__ x,
                                                const double* __restrict__ y,
                                                const double* __restrict__ z, int64_t n,
-                                               double4* __restrict__ P0,
                                                double4* __restrict__ orig,
-                                               int32_t* __restrict__ pnode,
                                                double* __restrict__ part, int* __restrict__ flag) {
     double mn[3] = {INFINITY, INFINITY, INFINITY};
     double mx[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -43,9 +43,7 @@ __global__ __launch_bounds__(kT) void k_ingest(const double* __restrict__ x,
     for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += (int64_t)gridDim.x * kT) {
         double a = x[i], b = y[i], c = z[i];
         bad |= !(isfinite(a) && isfinite(b) && isfinite(c));
-        P0[i] = make_double4(a, b, c, (double)i);
         orig[i] = make_double4(a, b, c, 0.0);
-        pnode[i] = 0;
         mn[0] = fmin(mn[0], a); mx[0] = fmax(mx[0], a);
         mn[1] = fmin(mn[1], b); mx[1] = fmax(mx[1], b);
         mn[2] = fmin(mn[2], c); mx[2] = fmax(mx[2], c);
@@ -65,6 +63,35 @@ __global__ __launch_bounds__(kT) void k_ingest(const double* __restrict__ x,
             v = threadIdx.x < 3 ? fmin(v, sh[threadIdx.x][k]) : fmax(v, sh[threadIdx.x][k]);
         part[blockIdx.x * 6 + threadIdx.x] = v;
     }
+}
+
+// A3: 30-bit Morton key of each particle on the root box (10 bits per axis,
+// the Eq. 2 function with b = 1024).
+__global__ __launch_bounds__(kT) void k_morton(const double4* __restrict__ orig, int64_t n,
+                                               const double* __restrict__ box,
+                                               uint32_t* __restrict__ keys,
+                                               int32_t* __restrict__ vals) {
+    int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (i >= n) return;
+    const double4 q = orig[i];
+    uint32_t kx = (uint32_t)subcell(q.x, box[0], box[3], 1024);
+    uint32_t ky = (uint32_t)subcell(q.y, box[1], box[4], 1024);
+    uint32_t kz = (uint32_t)subcell(q.z, box[2], box[5], 1024);
+    keys[i] = spread3(kx) | (spread3(ky) << 1) | (spread3(kz) << 2);
+    vals[i] = (int32_t)i;
+}
+
+// Particles in Morton order, all in the root cell (node 0).
+__global__ __launch_bounds__(kT) void k_gather(const double4* __restrict__ orig,
+                                               const int32_t* __restrict__ perm, int64_t n,
+                                               double4* __restrict__ P0,
+                                               int32_t* __restrict__ pnode) {
+    int64_t k = (int64_t)blockIdx.x * kT + threadIdx.x;
+    if (k >= n) return;
+    const int32_t i = perm[k];
+    const double4 q = orig[i];
+    P0[k] = make_double4(q.x, q.y, q.z, (double)i);
+    pnode[k] = 0;
 }
 
 __global__ __launch_bounds__(64) void k_rootbox(const double* __restrict__ part, int nparts,
@@ -92,27 +119,46 @@ __global__ void k_candidates(const Node* __restrict__ nodes, int64_t nb, int64_t
     hsize[i] = sum;
 }
 
-// Step 2: one histogram per candidate b (Eqs. 2 and 3).
+// Step 2: one histogram per candidate b (Eqs. 2 and 3).  Lanes of a
+// wavefront that fall in the same sub-cell share one atomic.
 __global__ __launch_bounds__(kT) void k_histogram(const double4* __restrict__ P,
                                                   const int32_t* __restrict__ pnode, int64_t n,
                                                   const Node* __restrict__ nodes, int64_t nb,
                                                   int64_t ne, int32_t s,
                                                   const int64_t* __restrict__ hoff,
                                                   int32_t* __restrict__ hist) {
-    int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (p >= n) return;
-    int32_t node = pnode[p];
-    if (node < nb || node >= ne) return;
-    const Node N = nodes[node];
-    const double4 q = P[p];
-    int64_t off = hoff[node - nb];
-    for (int bb = branching(N.n, s);; bb = halve(bb)) {
-        int cx = subcell(q.x, N.lo[0], N.hi[0], bb);
-        int cy = subcell(q.y, N.lo[1], N.hi[1], bb);
-        int cz = subcell(q.z, N.lo[2], N.hi[2], bb);
-        atomicAdd(&hist[off + cx + (int64_t)bb * (cy + (int64_t)bb * cz)], 1);
-        off += (int64_t)bb * bb * bb;
-        if (bb == 2) break;
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int32_t node = p < n ? pnode[p] : -1;
+    const bool act = node >= nb && node < ne;
+    Node N;
+    double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
+    int bb = 2, ncand = 0;
+    int64_t off = 0;
+    if (act) {
+        N = nodes[node];
+        q = P[p];
+        off = hoff[node - nb];
+        bb = branching(N.n, s);
+        for (int b = bb;; b = halve(b)) {
+            ++ncand;
+            if (b == 2) break;
+        }
+    }
+    int maxc = ncand;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) maxc = max(maxc, __shfl_xor(maxc, d, 64));
+    for (int k = 0; k < maxc; ++k) {
+        const bool a = act && k < ncand;
+        int64_t bin = 0;
+        if (a) {
+            int cx = subcell(q.x, N.lo[0], N.hi[0], bb);
+            int cy = subcell(q.y, N.lo[1], N.hi[1], bb);
+            int cz = subcell(q.z, N.lo[2], N.hi[2], bb);
+            bin = off + cx + (int64_t)bb * (cy + (int64_t)bb * cz);
+            off += (int64_t)bb * bb * bb;
+            bb = halve(bb);
+        }
+        wave_agg_inc(hist, bin, a);
     }
 }
 
@@ -279,7 +325,8 @@ __global__ __launch_bounds__(kT) void k_emit(Node* __restrict__ nodes, int64_t n
     }
 }
 
-// Step 5: scatter each particle of an active cell into its sub-cell segment.
+// Step 5: scatter each particle of an active cell into its sub-cell segment
+// (slots handed out per wavefront and sub-cell).
 __global__ __launch_bounds__(kT) void k_scatter(const double4* __restrict__ Psrc,
                                                 double4* __restrict__ Pdst,
                                                 const int32_t* __restrict__ pn_src,
@@ -290,23 +337,29 @@ __global__ __launch_bounds__(kT) void k_scatter(const double4* __restrict__ Psrc
                                                 const int32_t* __restrict__ cstart,
                                                 int32_t* __restrict__ cursor,
                                                 const int32_t* __restrict__ ctab) {
-    int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-    if (p >= n) return;
-    int32_t node = pn_src[p];
-    if (node < nb || node >= ne) return;
-    const Node N = nodes[node];
-    const int64_t i = node - nb;
-    const int b = bsel[i];
-    const double4 q = Psrc[p];
-    int cx = subcell(q.x, N.lo[0], N.hi[0], b);
-    int cy = subcell(q.y, N.lo[1], N.hi[1], b);
-    int cz = subcell(q.z, N.lo[2], N.hi[2], b);
-    int64_t c = cx + (int64_t)b * (cy + (int64_t)b * cz);
-    int64_t h = selofs[i] + c;
-    int32_t slot = atomicAdd(&cursor[h], 1);
-    int64_t dest = (int64_t)N.beg + cstart[h] + slot;
+    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
+    const int32_t node = p < n ? pn_src[p] : -1;
+    const bool act = node >= nb && node < ne;
+    int64_t hbin = 0, c = 0, nbeg = 0, nct = 0;
+    double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (act) {
+        const Node N = nodes[node];
+        const int64_t i = node - nb;
+        const int b = bsel[i];
+        q = Psrc[p];
+        int cx = subcell(q.x, N.lo[0], N.hi[0], b);
+        int cy = subcell(q.y, N.lo[1], N.hi[1], b);
+        int cz = subcell(q.z, N.lo[2], N.hi[2], b);
+        c = cx + (int64_t)b * (cy + (int64_t)b * cz);
+        hbin = selofs[i] + c;
+        nbeg = N.beg;
+        nct = N.ctab;
+    }
+    const int32_t slot = wave_agg_slot(cursor, hbin, act);
+    if (!act) return;
+    const int64_t dest = nbeg + cstart[hbin] + slot;
     Pdst[dest] = q;
-    int32_t code = ctab[N.ctab + c];
+    const int32_t code = ctab[nct + c];
     pn_dst[dest] = (code & kLeafBit) ? -1 : code;
 }
 
@@ -461,14 +514,31 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     int nblk = (int)std::min<int64_t>(kIngestBlocks, (n + kT - 1) / kT);
     part.reserve(sizeof(double) * 6 * nblk + 6 * sizeof(double));
     double* rootbox_d = part.as<double>() + 6 * nblk;
-    hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(kT), 0, st, x, y, z, n, P0.as<double4>(),
-                       t.orig.as<double4>(), pn0.as<int32_t>(), part.as<double>(), t.flag.as<int>());
+    hipLaunchKernelGGL(k_ingest, dim3(nblk), dim3(kT), 0, st, x, y, z, n, t.orig.as<double4>(),
+                       part.as<double>(), t.flag.as<int>());
     BT_LAUNCH();
     hipLaunchKernelGGL(k_rootbox, dim3(1), dim3(64), 0, st, part.as<double>(), nblk, rootbox_d);
     BT_LAUNCH();
     BT_HIP(hipMemcpyAsync(t.rootbox, rootbox_d, sizeof(double) * 6, hipMemcpyDeviceToHost, st));
     int flag = read1<int>(t.flag.p, st);
     if (flag) fail(BTREE_EINVAL, "btree_build: non-finite particle coordinate");
+
+    // Morton order of the particles (keys and permutation use the node-id
+    // and histogram buffers of the level loop as scratch).
+    {
+        W.mk0.reserve(sizeof(uint32_t) * n);
+        W.mk1.reserve(sizeof(uint32_t) * n);
+        W.mv0.reserve(sizeof(int32_t) * n);
+        W.mv1.reserve(sizeof(int32_t) * n);
+        hipLaunchKernelGGL(k_morton, dim3(grid_for(n, kT)), dim3(kT), 0, st, t.orig.as<double4>(), n,
+                           rootbox_d, W.mk0.as<uint32_t>(), W.mv0.as<int32_t>());
+        BT_LAUNCH();
+        radix_sort_pairs(W.mk0.as<uint32_t>(), W.mv0.as<int32_t>(), W.mk1.as<uint32_t>(),
+                         W.mv1.as<int32_t>(), n, 32, t, W.rcnt, W.roff, st);
+        hipLaunchKernelGGL(k_gather, dim3(grid_for(n, kT)), dim3(kT), 0, st, t.orig.as<double4>(),
+                           W.mv0.as<int32_t>(), n, P0.as<double4>(), pn0.as<int32_t>());
+        BT_LAUNCH();
+    }
 
     // Level loop state.
     int64_t nodes_cap = 1024, leaves_cap = 1024, ctab_cap = 4096;

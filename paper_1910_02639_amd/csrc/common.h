@@ -140,6 +140,7 @@ struct Work {
     DBuf hsize, hoff, hist, cstart, crank, cursor, bsel, selofs, nint, nleaf, ibase, lbase,
         ctsize, ctoff;
     DBuf mark, f, rank, l2, d2, newid, nc, coff;
+    DBuf mk0, mk1, mv0, mv1, rcnt, roff;  // Morton sort
 };
 
 // Phases timed with HIP events when btree_params.timing is set.
@@ -188,6 +189,7 @@ struct Timer {
 // The handle.
 struct Tree {
     int64_t n = 0;
+    bool valid = false;  // a tree is built
     btree_params prm{};
     int device = 0;
 
@@ -306,6 +308,8 @@ void scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, Tree& t,
 void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, Tree& t,
                         hipStream_t st, const int* guard = nullptr);
 
+void radix_sort_pairs(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n, int bits,
+                      Tree& t, DBuf& cnt, DBuf& off, hipStream_t st);
 void build_tree(Tree& t, const double* x, const double* y, const double* z,
                 hipStream_t st);
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets,

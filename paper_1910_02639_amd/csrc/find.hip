@@ -334,18 +334,23 @@ __global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
             atomicAdd(&stats->candidates, (unsigned long long)C);
         }
     } else {
-        if (qv) {
-            int64_t base = offsets[qidx];
-            const int64_t end = offsets[qidx + 1];
-            for (int k = 0; k < w; ++k) base += s_cnt[k][lane];
-            for (int kw = k0; kw < k1; kw += 32) {
-                uint32_t word = s_bits[(kw >> 5) * 64 + lane];
-                while (word) {
-                    int bpos = __ffs(word) - 1;
-                    word &= word - 1;
-                    if (base < end) nbrs[base] = Ent<F32>::key(s_cand[kw + bpos]);
-                    ++base;
-                }
+        // Rows out, one query per wavefront iteration: lane k owns bit word k
+        // (candidates 32k .. 32k+31, ascending original index), so a row is
+        // written as consecutive runs by consecutive lanes.
+        const int nwords = (C + 31) >> 5;
+        const int64_t myoff = qv ? offsets[qidx] : 0;
+        const int64_t myend = qv ? offsets[qidx + 1] : 0;
+        for (int q = w; q < ch.cnt; q += kWaves) {
+            uint32_t word = lane < nwords ? s_bits[lane * 64 + q] : 0u;
+            const int pc = __popc(word);
+            const int inc = wave_incl_scan(pc);
+            int64_t at = __shfl(myoff, q, 64) + (inc - pc);
+            const int64_t end = __shfl(myend, q, 64);
+            while (word) {
+                const int bpos = __ffs(word) - 1;
+                word &= word - 1;
+                if (at < end) nbrs[at] = Ent<F32>::key(s_cand[lane * 32 + bpos]);
+                ++at;
             }
         }
     }
@@ -418,12 +423,15 @@ __global__ void k_check_h(const double* __restrict__ h, int64_t n, int* __restri
 template <bool F32, int MODE>
 void launch_find(Tree& t, const double* h, int32_t* counts, const int64_t* offsets,
                  int32_t* nbrs, hipStream_t st) {
+    const int ph = MODE == kCount ? kPhCount : kPhFill;
+    t.timer.start(ph, st);
     hipLaunchKernelGGL((k_find<F32, MODE>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
                        t.chunks.as<Chunk>(), t.pos.as<double4>(), t.orig.as<double4>(),
                        t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
                        t.root_code, h, counts, offsets, nbrs, t.cflag.as<int32_t>(),
                        t.flag.as<int>(), t.stats.as<Stats>());
     BT_LAUNCH();
+    t.timer.stop(ph, st);
     hipLaunchKernelGGL((k_brute<MODE>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
                        t.chunks.as<Chunk>(), t.cflag.as<int32_t>(), t.pos.as<double4>(),
                        t.orig.as<double4>(), t.n, h, counts, offsets, nbrs, t.flag.as<int>());

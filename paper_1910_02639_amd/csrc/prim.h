@@ -13,6 +13,39 @@ __device__ __forceinline__ int lanes_below(uint64_t mask) {
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Adds, for every active lane, 1 to counter[idx] with one atomic per distinct
+// idx in the wavefront.  Cheap when neighbouring lanes share idx (particles
+// sorted along a space-filling curve).
+__device__ __forceinline__ void wave_agg_inc(int32_t* counter, int64_t idx, bool active) {
+    uint64_t rem = __ballot(active);
+    while (rem) {
+        const int leader = __ffsll((unsigned long long)rem) - 1;
+        const int64_t li = __shfl(idx, leader, 64);
+        const uint64_t peers = __ballot(active && idx == li);
+        if (lane_id() == leader) atomicAdd(&counter[li], (int32_t)__popcll(peers));
+        rem &= ~peers;
+    }
+}
+
+// Like wave_agg_inc, and returns the old value of counter[idx] plus the
+// number of lower lanes with the same idx (a unique slot per lane).
+__device__ __forceinline__ int32_t wave_agg_slot(int32_t* counter, int64_t idx, bool active) {
+    uint64_t rem = __ballot(active);
+    int32_t slot = 0;
+    while (rem) {
+        const int leader = __ffsll((unsigned long long)rem) - 1;
+        const int64_t li = __shfl(idx, leader, 64);
+        const bool mine = active && idx == li;
+        const uint64_t peers = __ballot(mine);
+        int32_t base = 0;
+        if (lane_id() == leader) base = atomicAdd(&counter[li], (int32_t)__popcll(peers));
+        base = __shfl(base, leader, 64);
+        if (mine) slot = base + lanes_below(peers);
+        rem &= ~peers;
+    }
+    return slot;
+}
+
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
     const int l = lane_id();

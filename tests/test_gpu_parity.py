@@ -255,3 +255,31 @@ def test_deterministic(prec):
     c = gpu_lists(x, y, z, h, "fp64" if prec == "fp32" else "fp32", bucket_size=16, beta=0.3)
     for u, v in zip(a[:3], c[:3]):
         assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_rebuild_reuses_handle(prec):
+    """btree_rebuild over a different set (and size) gives that set's lists;
+    phase timers accumulate across rebuilds."""
+    from paper_1910_02639_amd import btree
+    import torch
+    xa, ya, za, ha = W.plummer(50_000, 11)
+    xb, yb, zb, hb = W.uniform_cube(20_000, 12, 64.0)
+    A = to_dev(xa, ya, za, ha)
+    B = to_dev(xb, yb, zb, hb)
+    with btree.BTree(A[0], A[1], A[2], bucket_size=32, precision=prec, timing=True) as t:
+        c, o, nb = t.find(A[3])
+        assert_same_lists((c.cpu().numpy(), o.cpu().numpy(), nb.cpu().numpy()),
+                          oracle.lists(xa, ya, za, ha))
+        t.rebuild(B[0], B[1], B[2])
+        c, o, nb = t.find(B[3])
+        assert_same_lists((c.cpu().numpy(), o.cpu().numpy(), nb.cpu().numpy()),
+                          oracle.lists(xb, yb, zb, hb))
+        t.rebuild(A[0], A[1], A[2])
+        c, o, nb = t.find(A[3])
+        torch.cuda.synchronize()
+        assert_same_lists((c.cpu().numpy(), o.cpu().numpy(), nb.cpu().numpy()),
+                          oracle.lists(xa, ya, za, ha))
+        st = t.stats()
+        assert st["phase_calls"]["build"] == 3 and st["phase_ms"]["build"] > 0
+        assert st["phase_calls"]["count_kernel"] == 3 and st["phase_calls"]["fill_kernel"] == 3
