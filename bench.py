@@ -138,16 +138,16 @@ def main():
     ms_per_step = 1e3 * elapsed / a.steps
     value = n * a.steps / elapsed
 
-    # Dominant kernel of the search and its roofline.
-    kern = "count_kernel" if ph["count_kernel"] >= ph["fill_kernel"] else "fill_kernel"
+    # Dominant kernel of the search (the sweep: walk, stage, pair tests,
+    # rows) and its roofline.
+    kern = "sweep_kernel" if ph["sweep_kernel"] >= ph["place_kernel"] else "place_kernel"
     kms = ph[kern]
     tests = st["pair_tests"]
     ops = OPS_PER_TEST_F32 if a.precision == "fp32" else OPS_PER_TEST_F64
     achieved = tests * ops / (kms * 1e-3) / 1e12
     roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-            "frac": achieved / VALU_PEAK_TOPS, "kernel": "k_find<%s,%s>" % (
-                "fp32" if a.precision == "fp32" else "fp64",
-                "count" if kern == "count_kernel" else "fill"),
+            "frac": achieved / VALU_PEAK_TOPS, "kernel": "k_sweep<%s>" % (
+                "fp32" if a.precision == "fp32" else "fp64"),
             "traffic": load_traffic(kern, a.workload),
             "algorithmic_ops_per_launch": tests * ops}
     # Compulsory HBM bytes of the whole search (both passes), per particle:
@@ -170,7 +170,7 @@ def main():
                    "neighbours_total": total, "neighbours_mean": total / n},
         "phases_ms": ph,
         "search_particles_per_s": n / (find_ms * 1e-3),
-        "pair_tests_per_s": tests / (ph["count_kernel"] * 1e-3),
+        "pair_tests_per_s": tests / (ph["sweep_kernel"] * 1e-3),
         "pair_tests_per_particle": tests / n,
         "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, tests),
         "exhaustive_items": st["brute_chunks"],

@@ -90,7 +90,8 @@ typedef struct {
     int64_t candidates;     /* culled candidates staged, summed over items    */
     /* with params.timing = 1, device time of each phase summed over the
        calls since btree_build (btree_rebuild keeps counting):
-       [0] build, [1] search count kernel, [2] search fill kernel,
+       [0] build, [1] search sweep kernel (walk, stage, test, rows to the
+       handle's scratch), [2] placement kernel (rows into the caller's CSR),
        [3] whole pass 1, [4] whole pass 2; phase_calls counts the calls.   */
     double  phase_ms[5];
     int64_t phase_calls[5];

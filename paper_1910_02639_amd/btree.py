@@ -48,7 +48,7 @@ class Stats(ctypes.Structure):
                 ("brute_chunks", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("phase_ms", ctypes.c_double * 5), ("phase_calls", ctypes.c_int64 * 5)]
 
-PHASES = ["build", "count_kernel", "fill_kernel", "pass1", "pass2"]
+PHASES = ["build", "sweep_kernel", "place_kernel", "pass1", "pass2"]
 
 
 class BTreeError(RuntimeError):

@@ -409,12 +409,34 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
                                                    double4* __restrict__ pos, double blo0,
                                                    double blo1, double blo2, double bhi0,
                                                    double bhi1, double bhi2,
-                                                   Stats* __restrict__ stats) {
+                                                   int2* __restrict__ lrange) {
     __shared__ uint64_t key[kSortMax];
     __shared__ int32_t val[kSortMax];
     __shared__ int32_t ord[kSortMax];
+    __shared__ int32_t red[2][kT / 64];
     const Leaf L = leaves[blockIdx.x];
     const double4* src = (ldepth[blockIdx.x] & 1) ? P1 : P0;
+    // Smallest and largest original index of the leaf (bounds the index
+    // range of the candidates a search stages from it).
+    {
+        int mn = 0x7fffffff, mx = -1;
+        for (int k = threadIdx.x; k < L.cnt; k += kT) {
+            int v = (int)src[L.beg + k].w;
+            mn = min(mn, v);
+            mx = max(mx, v);
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            mn = min(mn, __shfl_xor(mn, d, 64));
+            mx = max(mx, __shfl_xor(mx, d, 64));
+        }
+        if (lane_id() == 0) { red[0][threadIdx.x >> 6] = mn; red[1][threadIdx.x >> 6] = mx; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < kT / 64; ++k) { mn = min(mn, red[0][k]); mx = max(mx, red[1][k]); }
+            lrange[blockIdx.x] = make_int2(mn, mx);
+        }
+    }
     if (L.cnt > kSortMax) {
         for (int k = threadIdx.x; k < L.cnt; k += kT) pos[L.beg + k] = src[L.beg + k];
         return;
@@ -683,10 +705,12 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
         BT_HIP(hipStreamSynchronize(st));
     }
 
+    t.lrange.reserve(sizeof(int2) * n_leaves);
     hipLaunchKernelGGL(k_leaf_final, dim3((unsigned)n_leaves), dim3(kT), 0, st,
                        t.leaves.as<Leaf>(), t.ldepth.as<int32_t>(), P0.as<double4>(),
                        P1.as<double4>(), t.pos.as<double4>(), t.rootbox[0], t.rootbox[1],
-                       t.rootbox[2], t.rootbox[3], t.rootbox[4], t.rootbox[5], dstats);
+                       t.rootbox[2], t.rootbox[3], t.rootbox[4], t.rootbox[5],
+                       t.lrange.as<int2>());
     BT_LAUNCH();
 
     // Shape statistics.

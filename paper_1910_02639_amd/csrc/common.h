@@ -144,7 +144,7 @@ struct Work {
 };
 
 // Phases timed with HIP events when btree_params.timing is set.
-enum Phase { kPhBuild = 0, kPhCount = 1, kPhFill = 2, kPhPass1 = 3, kPhPass2 = 4, kPhases = 5 };
+enum Phase { kPhBuild = 0, kPhSweep = 1, kPhPlace = 2, kPhPass1 = 3, kPhPass2 = 4, kPhases = 5 };
 
 struct Timer {
     hipEvent_t ev[kPhases][2] = {};
@@ -199,16 +199,20 @@ struct Tree {
     DBuf ctab;     // int32 child tables
     DBuf leaves;   // Leaf[n_leaves], memory order
     DBuf ldepth;   // int32 per leaf
+    DBuf lrange;   // int2 per leaf: smallest and largest original index
     DBuf chunks;   // Chunk[n_chunks]
     DBuf stats;    // Stats
     DBuf flag;     // int32 device flag (invalid data)
     DBuf cflag;    // int32 per chunk: exhaustive path needed
     DBuf scan_tmp; // scan block sums
     DBuf scal;     // small scalars (int64 total etc.)
+    DBuf scratch;  // int32 rows of the search, in work-item order
+    DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)
     Work ws;
     Timer timer;
 
     int64_t n_internal = 0, n_leaves = 0, n_chunks = 0, ctab_len = 0;
+    int64_t scap = 0;  // scratch capacity, entries
     int64_t depth = 0, max_leaf = 0, oversized = 0;
     int32_t root_code = kEmpty;
     double rootbox[6] = {0, 0, 0, 0, 0, 0};

@@ -39,6 +39,7 @@
 //    FP64 predicate on the original coordinates.
 #include "prim.h"
 
+#include <algorithm>
 #include <cfloat>
 
 namespace bt {
@@ -47,9 +48,11 @@ namespace {
 
 constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
-constexpr int kLMax = 1024;  // candidate leaves per item
-constexpr int kSMax = 512;   // walk stack entries
+constexpr int kLMax = 512;   // candidate leaves per item
+constexpr int kSMax = 256;   // walk stack entries
 constexpr int kCMax = 2048;  // staged candidates per item (both forms)
+constexpr int kBuckets = 256;       // original-index buckets of the staged list
+constexpr int kBucketSortMax = 48;  // a fuller bucket sorts the whole item instead
 
 enum { kCount = 0, kFill = 1 };
 
@@ -61,6 +64,80 @@ __device__ __forceinline__ bool p64(double xi, double yi, double zi, double R, d
     double dz = __dsub_rn(zi, zj);
     double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
     return d2 < __dmul_rn(R, R);
+}
+
+// Bit accumulation of the pair tests: word = 2*word + (d < lo) and
+// lword = 2*lword + (d < hi) for four consecutive candidates, with one
+// compare and one add-with-carry per bit (the compare's lane mask is the
+// carry-in).  All eight compares are issued before the first add so every
+// mask is read at least six instructions after it is written.
+__device__ __forceinline__ void push4_f32(uint32_t& word, uint32_t& lword, float d0, float d1,
+                                          float d2, float d3, float lo, float hi) {
+    uint64_t m0, m1, m2, m3, n0, n1, n2, n3, c;
+    asm volatile(
+        "v_cmp_lt_f32_e64 %[m0], %[d0], %[lo]\n\t"
+        "v_cmp_lt_f32_e64 %[n0], %[d0], %[hi]\n\t"
+        "v_cmp_lt_f32_e64 %[m1], %[d1], %[lo]\n\t"
+        "v_cmp_lt_f32_e64 %[n1], %[d1], %[hi]\n\t"
+        "v_cmp_lt_f32_e64 %[m2], %[d2], %[lo]\n\t"
+        "v_cmp_lt_f32_e64 %[n2], %[d2], %[hi]\n\t"
+        "v_cmp_lt_f32_e64 %[m3], %[d3], %[lo]\n\t"
+        "v_cmp_lt_f32_e64 %[n3], %[d3], %[hi]\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m0]\n\t"
+        "v_addc_co_u32_e64 %[l], %[c], %[l], %[l], %[n0]\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m1]\n\t"
+        "v_addc_co_u32_e64 %[l], %[c], %[l], %[l], %[n1]\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m2]\n\t"
+        "v_addc_co_u32_e64 %[l], %[c], %[l], %[l], %[n2]\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m3]\n\t"
+        "v_addc_co_u32_e64 %[l], %[c], %[l], %[l], %[n3]"
+        : [w] "+v"(word), [l] "+v"(lword), [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2),
+          [m3] "=&s"(m3), [n0] "=&s"(n0), [n1] "=&s"(n1), [n2] "=&s"(n2), [n3] "=&s"(n3),
+          [c] "=&s"(c)
+        : [d0] "v"(d0), [d1] "v"(d1), [d2] "v"(d2), [d3] "v"(d3), [lo] "v"(lo), [hi] "v"(hi));
+}
+
+// One candidate (tails of a block): same bits, two wait states spelled out.
+__device__ __forceinline__ void push1_f32(uint32_t& word, uint32_t& lword, float d, float lo,
+                                          float hi) {
+    uint64_t m, n, c;
+    asm volatile(
+        "v_cmp_lt_f32_e64 %[m], %[d], %[lo]\n\t"
+        "v_cmp_lt_f32_e64 %[n], %[d], %[hi]\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m]\n\t"
+        "v_addc_co_u32_e64 %[l], %[c], %[l], %[l], %[n]"
+        : [w] "+v"(word), [l] "+v"(lword), [m] "=&s"(m), [n] "=&s"(n), [c] "=&s"(c)
+        : [d] "v"(d), [lo] "v"(lo), [hi] "v"(hi));
+}
+
+// word = 2*word + (d < r2) for four / one candidates of the FP64 form.
+__device__ __forceinline__ void push4_f64(uint32_t& word, double d0, double d1, double d2,
+                                          double d3, double r2) {
+    uint64_t m0, m1, m2, m3, c;
+    asm volatile(
+        "v_cmp_lt_f64_e64 %[m0], %[d0], %[r]\n\t"
+        "v_cmp_lt_f64_e64 %[m1], %[d1], %[r]\n\t"
+        "v_cmp_lt_f64_e64 %[m2], %[d2], %[r]\n\t"
+        "v_cmp_lt_f64_e64 %[m3], %[d3], %[r]\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m0]\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m1]\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m2]\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m3]"
+        : [w] "+v"(word), [m0] "=&s"(m0), [m1] "=&s"(m1), [m2] "=&s"(m2), [m3] "=&s"(m3),
+          [c] "=&s"(c)
+        : [d0] "v"(d0), [d1] "v"(d1), [d2] "v"(d2), [d3] "v"(d3), [r] "v"(r2));
+}
+
+__device__ __forceinline__ void push1_f64(uint32_t& word, double d, double r2) {
+    uint64_t m, c;
+    asm volatile(
+        "v_cmp_lt_f64_e64 %[m], %[d], %[r]\n\t"
+        "s_nop 1\n\t"
+        "v_addc_co_u32_e64 %[w], %[c], %[w], %[w], %[m]"
+        : [w] "+v"(word), [m] "=&s"(m), [c] "=&s"(c)
+        : [d] "v"(d), [r] "v"(r2));
 }
 
 __device__ __forceinline__ float f32_down(double d) {
@@ -87,35 +164,43 @@ template <> struct Ent<false> {
     __device__ static void pad(double4& e) { e.w = 4294967296.0; }
 };
 
-template <bool F32, int MODE>
-__global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
-                                              const double4* __restrict__ pos,
-                                              const double4* __restrict__ orig,
-                                              const Node* __restrict__ nodes,
-                                              const int32_t* __restrict__ ctab,
-                                              const Leaf* __restrict__ leaves, int32_t root_code,
-                                              const double* __restrict__ h,
-                                              int32_t* __restrict__ counts,
-                                              const int64_t* __restrict__ offsets,
-                                              int32_t* __restrict__ nbrs,
-                                              int32_t* __restrict__ cflag,
-                                              const int* __restrict__ dflag,
-                                              Stats* __restrict__ stats) {
+// The single sweep: walk, stage, order by original index, test, rows out.
+template <bool F32>
+__global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
+                                               const double4* __restrict__ pos,
+                                               const double4* __restrict__ orig,
+                                               const Node* __restrict__ nodes,
+                                               const int32_t* __restrict__ ctab,
+                                               const Leaf* __restrict__ leaves,
+                                               const int2* __restrict__ lrange, int32_t root_code,
+                                               const double* __restrict__ h,
+                                               int32_t* __restrict__ counts,
+                                               int64_t* __restrict__ soff,
+                                               int32_t* __restrict__ scratch, int64_t scap,
+                                               unsigned long long* __restrict__ cursor,
+                                               int32_t* __restrict__ cflag, int* __restrict__ oflag,
+                                               const int* __restrict__ dflag,
+                                               Stats* __restrict__ stats) {
     using E = typename Ent<F32>::T;
     __shared__ E s_cand[kCMax];
-    __shared__ uint32_t s_bits[MODE == kFill ? (kCMax / 32) * 64 : 1];
+    __shared__ uint32_t s_bits[(kCMax / 32) * 64];
     __shared__ int32_t s_stack[kSMax];
     __shared__ int32_t s_leaf[kLMax];
-    __shared__ int32_t s_cnt[kWaves][64];
-    __shared__ int s_top, s_nleaf, s_ovf, s_cur, s_C;
+    __shared__ int32_t s_bcnt[kBuckets];
+    __shared__ int32_t s_bcur[kBuckets];
+    __shared__ int32_t s_qcnt[64];
+    __shared__ int32_t s_qoff[64];
+    __shared__ int64_t s_scan[kWaves + 1];
+    __shared__ int s_nleaf, s_ovf, s_kmin, s_kmax, s_C, s_big, s_total;
+    __shared__ unsigned long long s_base;
 
     if (*dflag) return;
     const int64_t ci = blockIdx.x;
-    if (MODE == kFill && cflag[ci]) return;
     const Chunk ch = chunks[ci];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
 
-    // Query of this lane.
+    // Queries: lane q of every wavefront holds query q of the item.
     const bool qv = lane < ch.cnt;
     const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int qidx = (int)qp.w;
@@ -124,14 +209,14 @@ __global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
     // Box E of the item.
     double elo[3], ehi[3];
     {
-        double q3[3] = {qp.x, qp.y, qp.z};
+        const double q3[3] = {qp.x, qp.y, qp.z};
         for (int l = 0; l < 3; ++l) {
             elo[l] = wave_min(qv ? q3[l] - R : INFINITY);
             ehi[l] = wave_max(qv ? q3[l] + R : -INFINITY);
         }
     }
 
-    // FP32 filter set-up (see the derivation at the top of the file).
+    // FP32 filter set-up (derivation at the top of the file).
     float ax = 0.f, ay = 0.f, az = 0.f, tlo = -1.f, thi = -1.f;
     double cx = 0.0, cy = 0.0, cz = 0.0;
     bool unsafe = false;
@@ -140,16 +225,16 @@ __global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
         cy = elo[1] + (ehi[1] - elo[1]) * 0.5;
         cz = elo[2] + (ehi[2] - elo[2]) * 0.5;
         const double up = 1.0 + 0x1p-50;
+        const double c3[3] = {cx, cy, cz};
+        const double q3[3] = {qp.x, qp.y, qp.z};
         double S[3];
-        double c3[3] = {cx, cy, cz};
-        double q3[3] = {qp.x, qp.y, qp.z};
         for (int l = 0; l < 3; ++l) {
-            double mb = fmax(c3[l] - elo[l], ehi[l] - c3[l]) * up;
-            double ma = wave_max(qv ? fabs(q3[l] - c3[l]) : 0.0) * up;
+            const double mb = fmax(c3[l] - elo[l], ehi[l] - c3[l]) * up;
+            const double ma = wave_max(qv ? fabs(q3[l] - c3[l]) : 0.0) * up;
             S[l] = (ma + mb) * up;
         }
-        double sn = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) * up;
-        double rmax = wave_max(R);
+        const double sn = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) * up;
+        const double rmax = wave_max(R);
         unsafe = !(sn < 0x1p100 && rmax < 0x1p100);
         const double u = 0x1p-24;
         const double eta = (0x1p-24 + 0x1p-52) * sn * (1.0 + 0x1p-40) + 8.0 * 0x1p-126;
@@ -157,9 +242,11 @@ __global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
         if (qv) {
             double A = R * (1.0 - 0x1p-48) - eta;
             if (A < 0.0) A = 0.0;
-            double tl = (1.0 - g3) * (1.0 - u) * (1.0 - u) * A * A * (1.0 - 0x1p-40) - 8.0 * 0x1p-126;
-            double B = R * (1.0 + 0x1p-48) + eta;
-            double th = (1.0 + g3) * (1.0 + u) * (1.0 + u) * B * B * (1.0 + 0x1p-40) + 8.0 * 0x1p-126;
+            const double tl =
+                (1.0 - g3) * (1.0 - u) * (1.0 - u) * A * A * (1.0 - 0x1p-40) - 8.0 * 0x1p-126;
+            const double B = R * (1.0 + 0x1p-48) + eta;
+            const double th =
+                (1.0 + g3) * (1.0 + u) * (1.0 + u) * B * B * (1.0 + 0x1p-40) + 8.0 * 0x1p-126;
             tlo = tl > 0.0 ? f32_down(tl) : 0.0f;
             thi = f32_up(th);
             ax = (float)(qp.x - cx);
@@ -169,96 +256,186 @@ __global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
     }
     const double r2q = qv ? __dmul_rn(R, R) : -1.0;
 
-    // Walk.
+    for (int b = t; b < kBuckets; b += kWG) s_bcnt[b] = 0;
     if (t == 0) {
-        s_top = 0;
-        s_nleaf = 0;
-        s_ovf = unsafe ? 1 : 0;
         s_C = 0;
+        s_big = 0;
+    }
+
+    // Walk (Algorithm 2 with Eq. 5 on E), by wavefront 0.  The six range
+    // bounds of a cell are computed by lanes 0..5, one each; lanes then
+    // take one sub-cell of the range each.
+    if (w == 0) {
+        int top = 0, nleaf = 0, ovf = unsafe ? 1 : 0;
         if (root_code & kLeafBit) {
-            s_leaf[0] = root_code & ~kLeafBit;
-            s_nleaf = 1;
+            if (lane == 0) s_leaf[0] = root_code & ~kLeafBit;
+            nleaf = 1;
         } else {
-            s_stack[0] = root_code;
-            s_top = 1;
+            if (lane == 0) s_stack[0] = root_code;
+            top = 1;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        while (top > 0 && !ovf) {
+            --top;
+            const int node = __builtin_amdgcn_readfirstlane(s_stack[top]);
+            const Node N = nodes[node];
+            const int b = N.b;
+            const int ax3 = lane < 3 ? lane : lane - 3;
+            const double ev = lane == 0 ? elo[0] : lane == 1 ? elo[1] : lane == 2 ? elo[2]
+                            : lane == 3 ? ehi[0] : lane == 4 ? ehi[1] : ehi[2];
+            const double nlo = ax3 == 0 ? N.lo[0] : ax3 == 1 ? N.lo[1] : N.lo[2];
+            const double nhi = ax3 == 0 ? N.hi[0] : ax3 == 1 ? N.hi[1] : N.hi[2];
+            const int r = lane < 6 ? subcell(ev, nlo, nhi, b) : 0;
+            const int rlo0 = __shfl(r, 0, 64), rlo1 = __shfl(r, 1, 64), rlo2 = __shfl(r, 2, 64);
+            const int nx = __builtin_amdgcn_readfirstlane(__shfl(r, 3, 64) - rlo0 + 1);
+            const int ny = __builtin_amdgcn_readfirstlane(__shfl(r, 4, 64) - rlo1 + 1);
+            const int nz = __builtin_amdgcn_readfirstlane(__shfl(r, 5, 64) - rlo2 + 1);
+            const int nxy = nx * ny;
+            const int T = nxy * nz;
+            for (int k0 = 0; k0 < T; k0 += 64) {
+                const int k = k0 + lane;
+                int32_t code = kEmpty;
+                if (k < T) {
+                    const int iz = k / nxy;
+                    const int rem = k - iz * nxy;
+                    const int iy = rem / nx;
+                    const int ix = rem - iy * nx;
+                    code = ctab[N.ctab + (rlo0 + ix) +
+                                (int64_t)b * ((rlo1 + iy) + (int64_t)b * (rlo2 + iz))];
+                }
+                const bool isl = code != kEmpty && (code & kLeafBit);
+                const bool isi = code != kEmpty && !(code & kLeafBit);
+                const uint64_t ml = __ballot(isl);
+                const uint64_t mi = __ballot(isi);
+                if (isl) {
+                    const int p = nleaf + lanes_below(ml);
+                    if (p < kLMax) s_leaf[p] = code & ~kLeafBit;
+                }
+                if (isi) {
+                    const int p = top + lanes_below(mi);
+                    if (p < kSMax) s_stack[p] = code;
+                }
+                nleaf += __popcll(ml);
+                top += __popcll(mi);
+                if (nleaf > kLMax || top > kSMax) {
+                    ovf = 1;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        // Index range of the candidate leaves.
+        int mn = 0x7fffffff, mx = -1;
+        if (!ovf) {
+            for (int li = lane; li < nleaf; li += 64) {
+                const int2 rr = lrange[s_leaf[li]];
+                mn = min(mn, rr.x);
+                mx = max(mx, rr.y);
+            }
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            mn = min(mn, __shfl_xor(mn, d, 64));
+            mx = max(mx, __shfl_xor(mx, d, 64));
+        }
+        if (lane == 0) {
+            s_nleaf = nleaf;
+            s_ovf = ovf;
+            s_kmin = mn;
+            s_kmax = mx;
         }
     }
     __syncthreads();
-    for (;;) {
-        if (t == 0) s_cur = (s_top > 0 && !s_ovf) ? s_stack[--s_top] : -1;
-        __syncthreads();
-        const int node = s_cur;
-        if (node < 0) break;
-        const Node N = nodes[node];
-        const int b = N.b;
-        int rlo[3], rhi[3];
-        for (int l = 0; l < 3; ++l) {
-            rlo[l] = subcell(elo[l], N.lo[l], N.hi[l], b);
-            rhi[l] = subcell(ehi[l], N.lo[l], N.hi[l], b);
+    if (s_ovf) {
+        if (t == 0) {
+            cflag[ci] = 1;
+            atomicAdd(&stats->brute, 1ull);
         }
-        const int nx = rhi[0] - rlo[0] + 1, ny = rhi[1] - rlo[1] + 1, nz = rhi[2] - rlo[2] + 1;
-        const int64_t T = (int64_t)nx * ny * nz;
-        for (int64_t k = t; k < T; k += kWG) {
-            int ix = rlo[0] + (int)(k % nx);
-            int iy = rlo[1] + (int)((k / nx) % ny);
-            int iz = rlo[2] + (int)(k / ((int64_t)nx * ny));
-            int32_t code = ctab[N.ctab + ix + (int64_t)b * (iy + (int64_t)b * iz)];
-            if (code == kEmpty) continue;
-            if (code & kLeafBit) {
-                int p = atomicAdd(&s_nleaf, 1);
-                if (p < kLMax) s_leaf[p] = code & ~kLeafBit;
-                else s_ovf = 1;
-            } else {
-                int p = atomicAdd(&s_top, 1);
-                if (p < kSMax) s_stack[p] = code;
-                else s_ovf = 1;
-            }
-        }
-        __syncthreads();
+        if (w == 0 && qv) soff[qidx] = -1;
+        return;
     }
+    const int nleaf = __builtin_amdgcn_readfirstlane(s_nleaf);
+    const int kmin = __builtin_amdgcn_readfirstlane(s_kmin);
+    const int kmax = __builtin_amdgcn_readfirstlane(s_kmax);
+    // Buckets of the original index: a monotone map of [kmin, kmax] onto
+    // 0..255, so sorting each bucket sorts the whole candidate list.
+    const float binv = (float)kBuckets / (float)((int64_t)kmax - kmin + 1);
 
-    // Stage the candidates inside E.
-    const int nleaf = s_nleaf < kLMax ? s_nleaf : kLMax;
-    if (!s_ovf) {
-        for (int li = w; li < nleaf; li += kWaves) {
-            const Leaf L = leaves[s_leaf[li]];
-            for (int p0 = 0; p0 < L.cnt; p0 += 64) {
-                const bool v = p0 + lane < L.cnt;
-                double4 P = v ? pos[L.beg + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
-                const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
-                                P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
-                const uint64_t m = __ballot(in);
-                if (m == 0) continue;
-                int base = 0;
-                if (lane == 0) base = atomicAdd(&s_C, __popcll(m));
-                base = __shfl(base, 0, 64);
-                if (in) {
-                    int slot = base + lanes_below(m);
-                    if (slot < kCMax) {
-                        if constexpr (F32) {
-                            s_cand[slot] = make_float4((float)(P.x - cx), (float)(P.y - cy),
-                                                       (float)(P.z - cz),
-                                                       __int_as_float((int)P.w));
-                        } else {
-                            s_cand[slot] = P;
-                        }
-                    }
+    // Stage, pass 1: count candidates inside E per index bucket.
+    int myC = 0;
+    for (int li = w; li < nleaf; li += kWaves) {
+        const Leaf L = leaves[s_leaf[li]];
+        for (int p0 = 0; p0 < L.cnt; p0 += 64) {
+            const bool v = p0 + lane < L.cnt;
+            const double4 P = v ? pos[L.beg + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+            const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
+                            P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
+            if (in) {
+                const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
+                atomicAdd(&s_bcnt[bk], 1);
+            }
+            myC += __popcll(__ballot(in));
+        }
+    }
+    if (lane == 0) atomicAdd(&s_C, myC);
+    __syncthreads();
+    const int C = __builtin_amdgcn_readfirstlane(s_C);
+    if (C > kCMax) {
+        if (t == 0) {
+            cflag[ci] = 1;
+            atomicAdd(&stats->brute, 1ull);
+        }
+        if (w == 0 && qv) soff[qidx] = -1;
+        return;
+    }
+    int bstart, bcount;
+    {
+        int64_t tot;
+        bcount = s_bcnt[t];
+        bstart = (int)block_excl_scan<kWG>(bcount, s_scan, &tot);
+        s_bcur[t] = bstart;
+        if (bcount > kBucketSortMax) s_big = 1;
+    }
+    __syncthreads();
+
+    // Stage, pass 2: place each candidate in its bucket.
+    for (int li = w; li < nleaf; li += kWaves) {
+        const Leaf L = leaves[s_leaf[li]];
+        for (int p0 = 0; p0 < L.cnt; p0 += 64) {
+            const bool v = p0 + lane < L.cnt;
+            const double4 P = v ? pos[L.beg + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+            const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
+                            P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
+            if (in) {
+                const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
+                const int slot = atomicAdd(&s_bcur[bk], 1);
+                if constexpr (F32) {
+                    s_cand[slot] = make_float4((float)(P.x - cx), (float)(P.y - cy),
+                                               (float)(P.z - cz), __int_as_float((int)P.w));
+                } else {
+                    s_cand[slot] = P;
                 }
             }
         }
     }
     __syncthreads();
-    const int C = s_C;
-    if (s_ovf || C > kCMax) {
-        if (MODE == kCount && t == 0) {
-            cflag[ci] = 1;
-            atomicAdd(&stats->brute, 1ull);
-        }
-        return;
-    }
 
-    if (MODE == kFill) {
-        // Sort the staged candidates by original index (bitonic, in LDS).
+    // Order by original index: insertion sort inside each bucket (thread b
+    // sorts bucket b); an item with a crowded bucket is sorted whole.
+    if (!s_big) {
+        for (int i = 1; i < bcount; ++i) {
+            const E e = s_cand[bstart + i];
+            const int key = Ent<F32>::key(e);
+            int j = i - 1;
+            while (j >= 0 && Ent<F32>::key(s_cand[bstart + j]) > key) {
+                s_cand[bstart + j + 1] = s_cand[bstart + j];
+                --j;
+            }
+            s_cand[bstart + j + 1] = e;
+        }
+    } else {
         int P2 = 1;
         while (P2 < C) P2 <<= 1;
         for (int k = C + t; k < P2; k += kWG) Ent<F32>::pad(s_cand[k]);
@@ -266,10 +443,10 @@ __global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
         for (int kk = 2; kk <= P2; kk <<= 1) {
             for (int j = kk >> 1; j > 0; j >>= 1) {
                 for (int a = t; a < P2; a += kWG) {
-                    int c = a ^ j;
+                    const int c = a ^ j;
                     if (c > a) {
-                        E ea = s_cand[a], ec = s_cand[c];
-                        bool upw = (a & kk) == 0;
+                        const E ea = s_cand[a], ec = s_cand[c];
+                        const bool upw = (a & kk) == 0;
                         if ((Ent<F32>::key(ea) > Ent<F32>::key(ec)) == upw) {
                             s_cand[a] = ec;
                             s_cand[c] = ea;
@@ -280,79 +457,154 @@ __global__ __launch_bounds__(kWG) void k_find(const Chunk* __restrict__ chunks,
             }
         }
     }
-
-    // Test: wavefront w sweeps candidates [k0, k1), 32-aligned blocks.
-    const int B = ((C + kWaves * 32 - 1) / (kWaves * 32)) * 32;
-    const int k0 = w * B;
-    const int k1 = (k0 + B < C) ? k0 + B : C;
-    int cnt = 0;
-    unsigned long long conf = 0;
-    for (int kw = k0; kw < k1; kw += 32) {
-        uint32_t word = 0;
-        const int kend = (kw + 32 < k1) ? kw + 32 : k1;
-        for (int k = kw; k < kend; ++k) {
-            const E e = s_cand[k];
-            bool acc;
-            if constexpr (F32) {
-                float tx = ax - e.x, ty = ay - e.y, tz = az - e.z;
-                float D = fmaf(tz, tz, fmaf(ty, ty, tx * tx));
-                acc = D < tlo;
-                const bool band = !acc && D <= thi;
-                const uint64_t bm = __ballot(band);
-                if (bm) {
-                    if (band) {
-                        const double4 o = orig[__float_as_int(e.w)];
-                        acc = p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z);
-                    }
-                    conf += __popcll(bm);
-                }
-            } else {
-                double dx = __dsub_rn(qp.x, e.x);
-                double dy = __dsub_rn(qp.y, e.y);
-                double dz = __dsub_rn(qp.z, e.z);
-                double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                      __dmul_rn(dz, dz));
-                acc = d2 < r2q;
-            }
-            word |= (uint32_t)acc << (k - kw);
-        }
-        cnt += __popc(word);
-        if (MODE == kFill) s_bits[(kw >> 5) * 64 + lane] = word;
-    }
-    s_cnt[w][lane] = cnt;
     __syncthreads();
 
-    if (MODE == kCount) {
-        if (w == 0 && qv) {
-            int tot = 0;
-            for (int k = 0; k < kWaves; ++k) tot += s_cnt[k][lane];
-            counts[qidx] = tot;
+    // Test: wavefront w sweeps candidates [k0, k1) (32-aligned) for its 64
+    // queries; one bit per (query, candidate), first candidate in the top
+    // bit of each 32-candidate word.  FP32 form: `word` collects D < T_lo
+    // (certain neighbours), `lword` collects D < T_hi (possible ones); the
+    // bits of lword & ~word are decided by the FP64 predicate.  D >= T_hi
+    // rules a pair out: below T_hi's real-valued bound whenever the pair
+    // could be a neighbour.
+    const int B = ((C + kWaves * 32 - 1) / (kWaves * 32)) * 32;
+    const int k0 = w * B;
+    const int k1 = min(k0 + B, C);
+    unsigned long long conf = 0;
+    for (int kw = k0; kw < k1; kw += 32) {
+        const int m = min(32, k1 - kw);
+        uint32_t word = 0;
+        if constexpr (F32) {
+            uint32_t lword = 0;
+            if (m == 32) {
+                for (int g = 0; g < 32; g += 8) {
+                    float4 e[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) e[j] = s_cand[kw + g + j];
+                    float D[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const float tx = ax - e[j].x, ty = ay - e[j].y, tz = az - e[j].z;
+                        D[j] = fmaf(tz, tz, fmaf(ty, ty, tx * tx));
+                    }
+                    push4_f32(word, lword, D[0], D[1], D[2], D[3], tlo, thi);
+                    push4_f32(word, lword, D[4], D[5], D[6], D[7], tlo, thi);
+                }
+            } else {
+                for (int j = 0; j < m; ++j) {
+                    const float4 e = s_cand[kw + j];
+                    const float tx = ax - e.x, ty = ay - e.y, tz = az - e.z;
+                    push1_f32(word, lword, fmaf(tz, tz, fmaf(ty, ty, tx * tx)), tlo, thi);
+                }
+                word <<= (32 - m);
+                lword <<= (32 - m);
+            }
+            uint32_t band = lword & ~word;
+            const uint64_t bm = __ballot(band != 0u);
+            if (bm) {
+                conf += __popcll(bm);
+                while (band) {
+                    const int j = __clz(band);
+                    band &= ~(0x80000000u >> j);
+                    const double4 o = orig[__float_as_int(s_cand[kw + j].w)];
+                    if (p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z)) word |= 0x80000000u >> j;
+                }
+            }
+        } else {
+            if (m == 32) {
+                for (int g = 0; g < 32; g += 4) {
+                    double4 e[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) e[j] = s_cand[kw + g + j];
+                    double d2[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double dx = __dsub_rn(qp.x, e[j].x);
+                        const double dy = __dsub_rn(qp.y, e[j].y);
+                        const double dz = __dsub_rn(qp.z, e[j].z);
+                        d2[j] = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                          __dmul_rn(dz, dz));
+                    }
+                    push4_f64(word, d2[0], d2[1], d2[2], d2[3], r2q);
+                }
+            } else {
+                for (int j = 0; j < m; ++j) {
+                    const double4 e = s_cand[kw + j];
+                    const double dx = __dsub_rn(qp.x, e.x);
+                    const double dy = __dsub_rn(qp.y, e.y);
+                    const double dz = __dsub_rn(qp.z, e.z);
+                    push1_f64(word, __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                              __dmul_rn(dz, dz)), r2q);
+                }
+                word <<= (32 - m);
+            }
         }
-        if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
-        if (t == 0) {
+        s_bits[(kw >> 5) * 64 + lane] = word;
+    }
+    if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
+    __syncthreads();
+
+    // Row lengths, then one scratch allocation for the item.
+    const int nwords = (C + 31) >> 5;
+    for (int q = w; q < ch.cnt; q += kWaves) {
+        const uint32_t word = lane < nwords ? s_bits[lane * 64 + q] : 0u;
+        const int tot = wave_sum(__popc(word));
+        if (lane == 0) s_qcnt[q] = tot;
+    }
+    __syncthreads();
+    if (w == 0) {
+        const int c = qv ? s_qcnt[lane] : 0;
+        const int inc = wave_incl_scan(c);
+        s_qoff[lane] = inc - c;
+        const int total = __shfl(inc, 63, 64);
+        if (lane == 0) {
+            s_total = total;
+            s_base = atomicAdd(cursor, (unsigned long long)total);
             atomicAdd(&stats->pair_tests, (unsigned long long)C * (unsigned long long)ch.cnt);
             atomicAdd(&stats->candidates, (unsigned long long)C);
         }
-    } else {
-        // Rows out, one query per wavefront iteration: lane k owns bit word k
-        // (candidates 32k .. 32k+31, ascending original index), so a row is
-        // written as consecutive runs by consecutive lanes.
-        const int nwords = (C + 31) >> 5;
-        const int64_t myoff = qv ? offsets[qidx] : 0;
-        const int64_t myend = qv ? offsets[qidx + 1] : 0;
-        for (int q = w; q < ch.cnt; q += kWaves) {
-            uint32_t word = lane < nwords ? s_bits[lane * 64 + q] : 0u;
-            const int pc = __popc(word);
-            const int inc = wave_incl_scan(pc);
-            int64_t at = __shfl(myoff, q, 64) + (inc - pc);
-            const int64_t end = __shfl(myend, q, 64);
-            while (word) {
-                const int bpos = __ffs(word) - 1;
-                word &= word - 1;
-                if (at < end) nbrs[at] = Ent<F32>::key(s_cand[lane * 32 + bpos]);
-                ++at;
-            }
+        if (qv) counts[qidx] = c;
+    }
+    __syncthreads();
+    const int64_t base = (int64_t)s_base;
+    if (base + s_total > scap) {
+        // Scratch too small this time: counts are right, rows are redone
+        // after the host grows the scratch to the total it now knows.
+        if (t == 0) atomicOr(oflag, 1);
+        if (w == 0 && qv) soff[qidx] = -2;
+        return;
+    }
+    if (w == 0 && qv) soff[qidx] = base + s_qoff[lane];
+    // Rows: one query per wavefront iteration, lane k owns bit word k.
+    for (int q = w; q < ch.cnt; q += kWaves) {
+        uint32_t word = lane < nwords ? s_bits[lane * 64 + q] : 0u;
+        const int pc = __popc(word);
+        const int inc = wave_incl_scan(pc);
+        int64_t at = base + s_qoff[q] + (inc - pc);
+        while (word) {
+            const int j = __clz(word);
+            word &= ~(0x80000000u >> j);
+            scratch[at++] = Ent<F32>::key(s_cand[lane * 32 + j]);
         }
+    }
+}
+
+// Rows from the scratch into the CSR array (original order, coalesced).
+__global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ counts,
+                                               const int64_t* __restrict__ soff,
+                                               const int64_t* __restrict__ offsets,
+                                               const int32_t* __restrict__ scratch,
+                                               int32_t* __restrict__ nbrs, int64_t n,
+                                               const int* __restrict__ dflag) {
+    if (*dflag) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t wid = ((int64_t)blockIdx.x * kWG + threadIdx.x) >> 6;
+    const int64_t nw = ((int64_t)gridDim.x * kWG) >> 6;
+    for (int64_t i = wid; i < n; i += nw) {
+        const int64_t so = soff[i];
+        if (so < 0) continue;
+        const int c = counts[i];
+        const int64_t o = offsets[i];
+        for (int k = lane; k < c; k += 64) nbrs[o + k] = scratch[so + k];
     }
 }
 
@@ -420,21 +672,21 @@ __global__ void k_check_h(const double* __restrict__ h, int64_t n, int* __restri
     if (__ballot(bad) && lane_id() == 0) atomicOr(dflag, 1);
 }
 
-template <bool F32, int MODE>
-void launch_find(Tree& t, const double* h, int32_t* counts, const int64_t* offsets,
-                 int32_t* nbrs, hipStream_t st) {
-    const int ph = MODE == kCount ? kPhCount : kPhFill;
-    t.timer.start(ph, st);
-    hipLaunchKernelGGL((k_find<F32, MODE>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
+template <bool F32>
+void launch_sweep(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
+    t.timer.start(kPhSweep, st);
+    hipLaunchKernelGGL((k_sweep<F32>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
                        t.chunks.as<Chunk>(), t.pos.as<double4>(), t.orig.as<double4>(),
                        t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
-                       t.root_code, h, counts, offsets, nbrs, t.cflag.as<int32_t>(),
-                       t.flag.as<int>(), t.stats.as<Stats>());
+                       t.lrange.as<int2>(), t.root_code, h, counts, t.soff.as<int64_t>(),
+                       t.scratch.as<int32_t>(), t.scap, t.scal.as<unsigned long long>(),
+                       t.cflag.as<int32_t>(), t.flag.as<int>() + 1, t.flag.as<int>(),
+                       t.stats.as<Stats>());
     BT_LAUNCH();
-    t.timer.stop(ph, st);
-    hipLaunchKernelGGL((k_brute<MODE>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
+    t.timer.stop(kPhSweep, st);
+    hipLaunchKernelGGL((k_brute<kCount>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
                        t.chunks.as<Chunk>(), t.cflag.as<int32_t>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), t.n, h, counts, offsets, nbrs, t.flag.as<int>());
+                       t.orig.as<double4>(), t.n, h, counts, nullptr, nullptr, t.flag.as<int>());
     BT_LAUNCH();
 }
 
@@ -442,29 +694,57 @@ void launch_find(Tree& t, const double* h, int32_t* counts, const int64_t* offse
 
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
     const bool f32 = t.prm.precision == BTREE_FP32_FILTER;
-    BT_HIP(hipMemsetAsync(t.flag.p, 0, sizeof(int32_t), st));
-    BT_HIP(hipMemsetAsync(t.cflag.p, 0, sizeof(int32_t) * t.n_chunks, st));
+    t.scal.reserve(64);
+    t.soff.reserve(sizeof(int64_t) * t.n);
+    if (t.scap == 0) {
+        t.scap = std::max<int64_t>(t.n * 128, 1 << 20);
+        t.scratch.reserve(sizeof(int32_t) * t.scap);
+    }
     BT_HIP(hipMemsetAsync(&t.stats.as<Stats>()->pair_tests, 0, 4 * sizeof(unsigned long long), st));
+    BT_HIP(hipMemsetAsync(t.flag.p, 0, 2 * sizeof(int32_t), st));
     hipLaunchKernelGGL(k_check_h, dim3(grid_for(t.n, 256) < 2048 ? grid_for(t.n, 256) : 2048),
                        dim3(256), 0, st, h, t.n, t.flag.as<int>());
     BT_LAUNCH();
-    if (f32) launch_find<true, kCount>(t, h, counts, nullptr, nullptr, st);
-    else launch_find<false, kCount>(t, h, counts, nullptr, nullptr, st);
-    scan_exclusive_i32(counts, offsets, t.n, t, st, t.flag.as<int>());
     int64_t total = 0;
-    int flag = 0;
-    BT_HIP(hipMemcpyAsync(&total, offsets + t.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-    BT_HIP(hipMemcpyAsync(&flag, t.flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
-    BT_HIP(hipStreamSynchronize(st));
-    if (flag) fail(BTREE_EINVAL, "btree_find_neighbors: h must be finite and >= 0");
+    for (int attempt = 0; attempt < 2; ++attempt) {
+        BT_HIP(hipMemsetAsync(t.cflag.p, 0, sizeof(int32_t) * t.n_chunks, st));
+        BT_HIP(hipMemsetAsync(t.scal.p, 0, sizeof(unsigned long long), st));
+        BT_HIP(hipMemsetAsync(t.flag.as<int>() + 1, 0, sizeof(int32_t), st));
+        if (f32) launch_sweep<true>(t, h, counts, st);
+        else launch_sweep<false>(t, h, counts, st);
+        scan_exclusive_i32(counts, offsets, t.n, t, st, t.flag.as<int>());
+        int flags[2] = {0, 0};
+        unsigned long long need = 0;
+        BT_HIP(hipMemcpyAsync(&total, offsets + t.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(flags, t.flag.p, sizeof flags, hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(&need, t.scal.p, sizeof need, hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
+        BT_HIP(hipStreamSynchronize(st));
+        if (flags[0]) fail(BTREE_EINVAL, "btree_find_neighbors: h must be finite and >= 0");
+        if (!flags[1]) break;
+        if (attempt == 1) fail(BTREE_EDEVICE, "btree_find_neighbors: scratch sizing failed");
+        // Rows did not fit: grow the scratch to the exact need and sweep again.
+        t.scap = (int64_t)need + (int64_t)need / 16 + 1024;
+        t.scratch.release();
+        t.scratch.reserve(sizeof(int32_t) * t.scap);
+        BT_HIP(hipMemsetAsync(&t.stats.as<Stats>()->pair_tests, 0, 4 * sizeof(unsigned long long), st));
+    }
     return total;
 }
 
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs, hipStream_t st) {
-    const bool f32 = t.prm.precision == BTREE_FP32_FILTER;
-    if (f32) launch_find<true, kFill>(t, h, nullptr, offsets, nbrs, st);
-    else launch_find<false, kFill>(t, h, nullptr, offsets, nbrs, st);
+    t.timer.start(kPhPlace, st);
+    const int64_t waves = t.n < 1 ? 1 : t.n;
+    unsigned grid = grid_for(waves, kWG / 64);
+    if (grid > 65536) grid = 65536;
+    hipLaunchKernelGGL(k_place, dim3(grid), dim3(kWG), 0, st, t.p1_counts, t.soff.as<int64_t>(),
+                       offsets, t.scratch.as<int32_t>(), nbrs, t.n, t.flag.as<int>());
+    BT_LAUNCH();
+    t.timer.stop(kPhPlace, st);
+    hipLaunchKernelGGL((k_brute<kFill>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
+                       t.chunks.as<Chunk>(), t.cflag.as<int32_t>(), t.pos.as<double4>(),
+                       t.orig.as<double4>(), t.n, h, nullptr, offsets, nbrs, t.flag.as<int>());
+    BT_LAUNCH();
 }
 
 }  // namespace bt

@@ -282,4 +282,4 @@ def test_rebuild_reuses_handle(prec):
                           oracle.lists(xa, ya, za, ha))
         st = t.stats()
         assert st["phase_calls"]["build"] == 3 and st["phase_ms"]["build"] > 0
-        assert st["phase_calls"]["count_kernel"] == 3 and st["phase_calls"]["fill_kernel"] == 3
+        assert st["phase_calls"]["sweep_kernel"] == 3 and st["phase_calls"]["place_kernel"] == 3
