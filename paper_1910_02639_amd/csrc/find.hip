@@ -50,7 +50,8 @@ constexpr int kWG = 256;
 constexpr int kWaves = kWG / 64;
 constexpr int kLMax = 512;   // candidate leaves per item
 constexpr int kSMax = 256;   // walk stack entries
-constexpr int kCMax = 2048;  // staged candidates per item (both forms)
+constexpr int kCMax = 1536;  // staged candidates per item (both forms)
+constexpr int kMaxWords = ((kCMax / 4) + 31) / 32;  // bit words per lane and wavefront
 constexpr int kBuckets = 256;       // original-index buckets of the staged list
 constexpr int kBucketSortMax = 48;  // a fuller bucket sorts the whole item instead
 
@@ -155,12 +156,12 @@ __device__ __forceinline__ float f32_up(double d) {
 template <bool F32> struct Ent;
 template <> struct Ent<true> {
     using T = float4;
-    __device__ static int key(const float4& e) { return __float_as_int(e.w); }
+    __device__ static int key(float4 e) { return __float_as_int(e.w); }
     __device__ static void pad(float4& e) { e.w = __int_as_float(0x7fffffff); }
 };
 template <> struct Ent<false> {
     using T = double4;
-    __device__ static int key(const double4& e) { return e.w > 2147483647.0 ? 0x7fffffff : (int)e.w; }
+    __device__ static int key(double4 e) { return e.w > 2147483647.0 ? 0x7fffffff : (int)e.w; }
     __device__ static void pad(double4& e) { e.w = 4294967296.0; }
 };
 
@@ -183,7 +184,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                Stats* __restrict__ stats) {
     using E = typename Ent<F32>::T;
     __shared__ E s_cand[kCMax];
-    __shared__ uint32_t s_bits[(kCMax / 32) * 64];
+    __shared__ int32_t s_cnt[kWaves][64];
     __shared__ int32_t s_stack[kSMax];
     __shared__ int32_t s_leaf[kLMax];
     __shared__ int32_t s_bcnt[kBuckets];
@@ -399,6 +400,20 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         if (bcount > kBucketSortMax) s_big = 1;
     }
     __syncthreads();
+    // A crowded bucket sorts the whole list with a bitonic network padded to
+    // a power of two; if that does not fit the buffer, take the exhaustive path.
+    if (s_big) {
+        int P2 = 1;
+        while (P2 < C) P2 <<= 1;
+        if (P2 > kCMax) {
+            if (t == 0) {
+                cflag[ci] = 1;
+                atomicAdd(&stats->brute, 1ull);
+            }
+            if (w == 0 && qv) soff[qidx] = -1;
+            return;
+        }
+    }
 
     // Stage, pass 2: place each candidate in its bucket.
     for (int li = w; li < nleaf; li += kWaves) {
@@ -429,9 +444,10 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
             const E e = s_cand[bstart + i];
             const int key = Ent<F32>::key(e);
             int j = i - 1;
-            while (j >= 0 && Ent<F32>::key(s_cand[bstart + j]) > key) {
-                s_cand[bstart + j + 1] = s_cand[bstart + j];
-                --j;
+            for (; j >= 0; --j) {
+                const E f = s_cand[bstart + j];
+                if (Ent<F32>::key(f) <= key) break;
+                s_cand[bstart + j + 1] = f;
             }
             s_cand[bstart + j + 1] = e;
         }
@@ -469,6 +485,13 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     const int B = ((C + kWaves * 32 - 1) / (kWaves * 32)) * 32;
     const int k0 = w * B;
     const int k1 = min(k0 + B, C);
+    const int nw = (k1 > k0) ? (k1 - k0 + 31) >> 5 : 0;  // words of this wavefront, <= kMaxWords
+    // The words of a lane live in registers as a shift queue: each new word
+    // enters at the top, so after nw words they sit in wq[kMaxWords - nw ..].
+    uint32_t wq[kMaxWords];
+#pragma unroll
+    for (int i = 0; i < kMaxWords; ++i) wq[i] = 0u;
+    int hits = 0;
     unsigned long long conf = 0;
     for (int kw = k0; kw < k1; kw += 32) {
         const int m = min(32, k1 - kw);
@@ -538,21 +561,21 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                 word <<= (32 - m);
             }
         }
-        s_bits[(kw >> 5) * 64 + lane] = word;
+        hits += __popc(word);
+#pragma unroll
+        for (int i = 0; i + 1 < kMaxWords; ++i) wq[i] = wq[i + 1];
+        wq[kMaxWords - 1] = word;
     }
     if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
+    s_cnt[w][lane] = hits;
     __syncthreads();
 
     // Row lengths, then one scratch allocation for the item.
-    const int nwords = (C + 31) >> 5;
-    for (int q = w; q < ch.cnt; q += kWaves) {
-        const uint32_t word = lane < nwords ? s_bits[lane * 64 + q] : 0u;
-        const int tot = wave_sum(__popc(word));
-        if (lane == 0) s_qcnt[q] = tot;
-    }
-    __syncthreads();
     if (w == 0) {
-        const int c = qv ? s_qcnt[lane] : 0;
+        int c = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) c += s_cnt[k][lane];
+        if (!qv) c = 0;
         const int inc = wave_incl_scan(c);
         s_qoff[lane] = inc - c;
         const int total = __shfl(inc, 63, 64);
@@ -574,21 +597,31 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         return;
     }
     if (w == 0 && qv) soff[qidx] = base + s_qoff[lane];
-    // Rows: one query per wavefront iteration, lane k owns bit word k.
-    for (int q = w; q < ch.cnt; q += kWaves) {
-        uint32_t word = lane < nwords ? s_bits[lane * 64 + q] : 0u;
-        const int pc = __popc(word);
-        const int inc = wave_incl_scan(pc);
-        int64_t at = base + s_qoff[q] + (inc - pc);
-        while (word) {
-            const int j = __clz(word);
-            word &= ~(0x80000000u >> j);
-            scratch[at++] = Ent<F32>::key(s_cand[lane * 32 + j]);
+    // Rows: lane q of wavefront w writes the hits of its block right after
+    // those of the blocks of lower wavefronts (ascending original index).
+    if (qv) {
+        int64_t at = base + s_qoff[lane];
+        for (int k = 0; k < w; ++k) at += s_cnt[k][lane];
+#pragma unroll
+        for (int i = 0; i < kMaxWords; ++i) {
+            const int wi = i - (kMaxWords - nw);  // word index within the block
+            if (wi >= 0) {
+                uint32_t word = wq[i];
+                const int kb = k0 + 32 * wi;
+                while (word) {
+                    const int j = __clz(word);
+                    word &= ~(0x80000000u >> j);
+                    scratch[at++] = Ent<F32>::key(s_cand[kb + j]);
+                }
+            }
         }
     }
 }
 
-// Rows from the scratch into the CSR array (original order, coalesced).
+// Rows from the scratch into the CSR array (original order, coalesced).  A
+// wavefront takes 64 consecutive rows; lane r first loads row r's length,
+// source and destination, then the wavefront copies the rows one by one with
+// those values broadcast from the owning lane.
 __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ counts,
                                                const int64_t* __restrict__ soff,
                                                const int64_t* __restrict__ offsets,
@@ -599,12 +632,23 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
     const int lane = threadIdx.x & 63;
     const int64_t wid = ((int64_t)blockIdx.x * kWG + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * kWG) >> 6;
-    for (int64_t i = wid; i < n; i += nw) {
-        const int64_t so = soff[i];
-        if (so < 0) continue;
-        const int c = counts[i];
-        const int64_t o = offsets[i];
-        for (int k = lane; k < c; k += 64) nbrs[o + k] = scratch[so + k];
+    for (int64_t r0 = wid * 64; r0 < n; r0 += nw * 64) {
+        const int64_t i = r0 + lane;
+        int64_t so = -1, o = 0;
+        int c = 0;
+        if (i < n) {
+            so = soff[i];
+            c = counts[i];
+            o = offsets[i];
+        }
+        const int rows = (int)min((int64_t)64, n - r0);
+        for (int r = 0; r < rows; ++r) {
+            const int64_t rso = __shfl(so, r, 64);
+            if (rso < 0) continue;
+            const int rc = __shfl(c, r, 64);
+            const int64_t ro = __shfl(o, r, 64);
+            for (int k = lane; k < rc; k += 64) nbrs[ro + k] = scratch[rso + k];
+        }
     }
 }
 
@@ -734,9 +778,9 @@ int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, 
 
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs, hipStream_t st) {
     t.timer.start(kPhPlace, st);
-    const int64_t waves = t.n < 1 ? 1 : t.n;
-    unsigned grid = grid_for(waves, kWG / 64);
-    if (grid > 65536) grid = 65536;
+    const int64_t waves = (t.n + 63) / 64;
+    unsigned grid = grid_for(waves < 1 ? 1 : waves, kWG / 64);
+    if (grid > 8192) grid = 8192;
     hipLaunchKernelGGL(k_place, dim3(grid), dim3(kWG), 0, st, t.p1_counts, t.soff.as<int64_t>(),
                        offsets, t.scratch.as<int32_t>(), nbrs, t.n, t.flag.as<int>());
     BT_LAUNCH();

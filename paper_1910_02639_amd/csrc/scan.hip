@@ -84,7 +84,92 @@ void scan_impl(const In* in, int64_t* out, int64_t n, Tree& t, hipStream_t st,
     BT_LAUNCH();
 }
 
+// Variants whose length lives in device memory (*nptr <= ncap): launched for
+// the capacity, tiles past the length do nothing.  No host read is needed, so
+// they can run inside a captured graph.
+template <class In>
+__global__ __launch_bounds__(kT) void k_tile_sum_dev(const In* __restrict__ in,
+                                                     const int32_t* __restrict__ nptr,
+                                                     int64_t* __restrict__ tsum) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    const int64_t n = *nptr;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    if (base >= n) {
+        if (threadIdx.x == 0) tsum[blockIdx.x] = 0;
+        return;
+    }
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t k = base + i * kT + threadIdx.x;
+        if (k < n) s += (int64_t)in[k];
+    }
+    s = block_sum<kT>(s, sh);
+    if (threadIdx.x == 0) tsum[blockIdx.x] = s;
+}
+
+template <class In>
+__global__ __launch_bounds__(kT) void k_tile_scan_dev(const In* __restrict__ in,
+                                                      const int32_t* __restrict__ nptr,
+                                                      const int64_t* __restrict__ tsum,
+                                                      int64_t ntiles, int64_t* __restrict__ out) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    const int64_t n = *nptr;
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = tsum[ntiles];
+    if ((int64_t)blockIdx.x * kTile >= n) return;
+    const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    int64_t v[kItems];
+    int64_t s = 0;
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t k = base + i;
+        v[i] = k < n ? (int64_t)in[k] : 0;
+        s += v[i];
+    }
+    int64_t tot;
+    int64_t ex = block_excl_scan<kT>(s, sh, &tot) + tsum[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kItems; ++i) {
+        int64_t k = base + i;
+        if (k < n) out[k] = ex;
+        ex += v[i];
+    }
+}
+
+template <class In>
+void scan_dev_impl(const In* in, int64_t* out, const int32_t* nptr, int64_t ncap, Tree& t,
+                   hipStream_t st) {
+    int64_t ntiles = (ncap + kTile - 1) / kTile;
+    if (ntiles < 1) ntiles = 1;
+    if (t.scan_tmp.bytes < sizeof(int64_t) * (size_t)(ntiles + 1))
+        fail(BTREE_EDEVICE, "scan workspace not reserved");
+    int64_t* ts = t.scan_tmp.as<int64_t>();
+    hipLaunchKernelGGL(k_tile_sum_dev<In>, dim3((unsigned)ntiles), dim3(kT), 0, st, in, nptr, ts);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_scan_tiles, dim3(1), dim3(kT), 0, st, ts, ntiles);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_tile_scan_dev<In>, dim3((unsigned)ntiles), dim3(kT), 0, st, in, nptr, ts,
+                       ntiles, out);
+    BT_LAUNCH();
+}
+
 }  // namespace
+
+void scan_reserve(Tree& t, int64_t ncap) {
+    int64_t ntiles = (ncap + kTile - 1) / kTile;
+    if (ntiles < 1) ntiles = 1;
+    t.scan_tmp.reserve(sizeof(int64_t) * (size_t)(ntiles + 1));
+}
+
+void scan_dev_i32(const int32_t* in, int64_t* out, const int32_t* nptr, int64_t ncap, Tree& t,
+                  hipStream_t st) {
+    scan_dev_impl<int32_t>(in, out, nptr, ncap, t, st);
+}
+
+void scan_dev_i64(const int64_t* in, int64_t* out, const int32_t* nptr, int64_t ncap, Tree& t,
+                  hipStream_t st) {
+    scan_dev_impl<int64_t>(in, out, nptr, ncap, t, st);
+}
 
 void scan_exclusive_i32(const int32_t* in, int64_t* out, int64_t n, Tree& t, hipStream_t st,
                         const int* guard) {
