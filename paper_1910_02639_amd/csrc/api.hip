@@ -74,9 +74,10 @@ static void do_build(Tree* t, const double* x, const double* y, const double* z,
     t->host_stats = Stats{};
     t->timer.on = t->prm.timing != 0;
     t->stats.reserve(sizeof(Stats));
-    t->flag.reserve(sizeof(int32_t) * 4);
     t->timer.start(kPhBuild, st);
     if (n > 0) {
+        const int64_t off[2] = {0, n};
+        plan_sets(*t, 1, off, &t->prm);
         build_tree(*t, x, y, z, st);
     } else {
         BT_HIP(hipMemsetAsync(t->stats.p, 0, sizeof(Stats), st));

@@ -101,7 +101,7 @@ struct DBuf {
 constexpr int32_t kEmpty = -1;         // child-table entry of an empty sub-cell
 constexpr int32_t kLeafBit = 1 << 30;  // child-table entry flag: a leaf id
 
-// An internal cell (split by Algorithm 1).  72 bytes.
+// An internal cell (split by Algorithm 1).  80 bytes.
 struct Node {
     double lo[3];      // cell box
     double hi[3];
@@ -110,6 +110,8 @@ struct Node {
     int32_t n;         // particles in the cell
     int32_t beg;       // first particle of the cell's segment
     int32_t depth;     // root = 0
+    int32_t set;       // particle set the cell belongs to
+    int32_t pad;
 };
 
 struct Leaf {
@@ -121,6 +123,8 @@ struct Leaf {
 struct Chunk {
     int32_t beg;
     int32_t cnt;
+    int32_t set;
+    int32_t pad;
 };
 
 constexpr int kGroup = 64;  // queries per work item (one per lane)
@@ -134,13 +138,65 @@ struct Stats {  // device-side counters
     unsigned long long b_hist[65];
 };
 
+// One independent particle set (a batch holds several, a tree one).
+struct SetDev {
+    int64_t beg;       // first particle, original and sorted numbering
+    int64_t n;         // particles
+    double alpha, beta;
+    int32_t s;         // bucket size
+    int32_t max_depth;
+    int32_t root;      // child code of the root cell (node id, leaf id | kLeafBit, or kEmpty)
+    int32_t pad;
+    double box[6];     // root box: lo x, y, z, hi x, y, z
+};
+
+// Tiles of at most kTileN particles, never straddling two sets.
+struct Tile {
+    int32_t set;
+    int32_t pad;
+    int64_t beg, end;
+};
+constexpr int64_t kTileN = 8192;
+
+// Overflow bits of Ctl::overflow (a pool was too small for this input).
+enum { kOvfNodes = 1, kOvfLeaves = 2, kOvfCtab = 4, kOvfHist = 8, kOvfLevels = 16,
+       kOvfScratch = 32, kOvfCapacity = 64, kOvfChunks = 128 };
+
+// Device control block of a build and its search: every level reads its
+// cell range from here, so no host round trip is needed between launches.
+struct Ctl {
+    int32_t cur_nb, cur_ne;     // cells of the level being split
+    int32_t lvm;                // cur_ne - cur_nb (a device length for scans)
+    int32_t pad0;
+    int32_t next_nb, next_ne;   // cells of the next level
+    int32_t n_nodes, n_leaves;  // allocated so far
+    int64_t ct_len;             // child-table entries allocated
+    int64_t hist_len;           // histogram entries of the current level
+    int32_t lv_int0, lv_leaf0;  // first node / leaf id given to this level's children
+    int64_t lv_ct0;             // first child-table entry of this level
+    int32_t level_ok;           // the current level fits its pools
+    int32_t overflow;           // kOvf* bits
+    int32_t data_bad;           // non-finite coordinate or h
+    int32_t n_chunks;           // search work items
+    int32_t depth;              // deepest leaf
+    int32_t max_leaf;           // largest leaf
+    int32_t oversized;          // leaves above their set's s
+    int32_t levels;             // levels that had cells to split
+    uint32_t queue;             // next search work item (atomic)
+    uint32_t nbrute;            // work items on the exhaustive path (atomic)
+    unsigned long long cursor;  // scratch allocation (atomic)
+};
+
+constexpr int kPersistBlocks = 2048;  // grid of the persistent per-cell / per-item kernels
+
 // Build workspace, kept by the handle so that rebuilds reuse its memory.
 struct Work {
     DBuf P0, P1, pn0, pn1, part;
     DBuf hsize, hoff, hist, cstart, crank, cursor, bsel, selofs, nint, nleaf, ibase, lbase,
         ctsize, ctoff;
-    DBuf mark, f, rank, l2, d2, newid, nc, coff;
+    DBuf mark, f, rank, newid, nc, coff;
     DBuf mk0, mk1, mv0, mv1, rcnt, roff;  // Morton sort
+    DBuf tiles, settile;                   // ingest tiles and their first tile per set
 };
 
 // Phases timed with HIP events when btree_params.timing is set.
@@ -199,13 +255,15 @@ struct Tree {
     DBuf ctab;     // int32 child tables
     DBuf leaves;   // Leaf[n_leaves], memory order
     DBuf ldepth;   // int32 per leaf
+    DBuf leaves2, ldepth2;  // the other copy (leaf renumbering ping-pongs)
+    DBuf sets;     // SetDev[nsets]
+    DBuf ctl;      // Ctl
+    DBuf tot;      // int64 per set boundary: offsets at set starts (batch totals)
     DBuf lrange;   // int2 per leaf: smallest and largest original index
     DBuf chunks;   // Chunk[n_chunks]
     DBuf stats;    // Stats
-    DBuf flag;     // int32 device flag (invalid data)
-    DBuf cflag;    // int32 per chunk: exhaustive path needed
+    DBuf blist;    // int32 work-item ids taken by the exhaustive path
     DBuf scan_tmp; // scan block sums
-    DBuf scal;     // small scalars (int64 total etc.)
     DBuf scratch;  // int32 rows of the search, in work-item order
     DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)
     Work ws;
@@ -213,6 +271,15 @@ struct Tree {
 
     int64_t n_internal = 0, n_leaves = 0, n_chunks = 0, ctab_len = 0;
     int64_t scap = 0;  // scratch capacity, entries
+    int64_t chunk_cap = 0;  // work items a captured search launches for
+    // sets and pool capacities
+    int32_t nsets = 1;
+    std::vector<int64_t> set_off;        // nsets + 1, host
+    std::vector<btree_params> set_prm;   // per set
+    int64_t ntiles = 0;
+    int64_t node_cap = 0, ctab_cap = 0, hist_cap = 0, leaf_cap = 0, level_cap = 0;
+    int32_t levels_seen = 0;
+    Ctl host_ctl{};
     int64_t depth = 0, max_leaf = 0, oversized = 0;
     int32_t root_code = kEmpty;
     double rootbox[6] = {0, 0, 0, 0, 0, 0};
@@ -240,7 +307,7 @@ __host__ __device__ inline int subcell(double x, double lo, double hi, int b) {
     if (!(w > 0.0)) return 0;
     double t = (x - lo) / w;
     double v = floor(t * (double)b);
-    if (v < 0.0) return 0;
+    if (!(v >= 0.0)) return 0;  // below the box (or not a number)
     if (v > (double)(b - 1)) return b - 1;
     return (int)v;
 }
@@ -314,8 +381,28 @@ void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, Tree& t,
 
 void radix_sort_pairs(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n, int bits,
                       Tree& t, DBuf& cnt, DBuf& off, hipStream_t st);
+void scan_reserve(Tree& t, int64_t ncap);
+void scan_dev_i32(const int32_t* in, int64_t* out, const int32_t* nptr, int64_t ncap, Tree& t,
+                  hipStream_t st);
+void scan_dev_i64(const int64_t* in, int64_t* out, const int32_t* nptr, int64_t ncap, Tree& t,
+                  hipStream_t st);
+
+// Sets the handle up for nsets sets (offsets on the host) and sizes all pools.
+void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off, const btree_params* prm);
+// Queues BuildTree of every set; `levels` level groups (no host reads when
+// eager is false).  With eager, the host stops as soon as a level is empty.
+void build_queue(Tree& t, const double* x, const double* y, const double* z, int levels,
+                 bool eager, hipStream_t st);
+// Eager build: queue, wait, grow pools and redo on overflow.
 void build_tree(Tree& t, const double* x, const double* y, const double* z,
                 hipStream_t st);
+// Search queued without host reads (for graphs): pass 1, then pass 2 into
+// nbrs of `capacity` entries (nothing written if the lists do not fit), then
+// per-set totals when `totals` is non-null.
+void find_queue(Tree& t, const double* h, int32_t* counts, int64_t* offsets, int32_t* nbrs,
+                int64_t capacity, int64_t* totals, hipStream_t st);
+// Sizes the search scratch for at least `entries` list entries.
+void find_reserve(Tree& t, int64_t entries);
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets,
                    hipStream_t st);
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,

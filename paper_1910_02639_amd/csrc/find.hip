@@ -165,23 +165,23 @@ template <> struct Ent<false> {
     __device__ static void pad(double4& e) { e.w = 4294967296.0; }
 };
 
-// The single sweep: walk, stage, order by original index, test, rows out.
+// One work item of the sweep: walk, stage, order by original index, test,
+// rows out.  Called by every thread of the workgroup with the same item.
 template <bool F32>
-__global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
-                                               const double4* __restrict__ pos,
-                                               const double4* __restrict__ orig,
-                                               const Node* __restrict__ nodes,
-                                               const int32_t* __restrict__ ctab,
-                                               const Leaf* __restrict__ leaves,
-                                               const int2* __restrict__ lrange, int32_t root_code,
-                                               const double* __restrict__ h,
-                                               int32_t* __restrict__ counts,
-                                               int64_t* __restrict__ soff,
-                                               int32_t* __restrict__ scratch, int64_t scap,
-                                               unsigned long long* __restrict__ cursor,
-                                               int32_t* __restrict__ cflag, int* __restrict__ oflag,
-                                               const int* __restrict__ dflag,
-                                               Stats* __restrict__ stats) {
+__device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict__ chunks,
+                                           const double4* __restrict__ pos,
+                                           const double4* __restrict__ orig,
+                                           const Node* __restrict__ nodes,
+                                           const int32_t* __restrict__ ctab,
+                                           const Leaf* __restrict__ leaves,
+                                           const int2* __restrict__ lrange,
+                                           const SetDev* __restrict__ sets,
+                                           const double* __restrict__ h,
+                                           int32_t* __restrict__ counts,
+                                           int64_t* __restrict__ soff,
+                                           int32_t* __restrict__ scratch, int64_t scap,
+                                           Ctl* __restrict__ ctl, int32_t* __restrict__ blist,
+                                           Stats* __restrict__ stats) {
     using E = typename Ent<F32>::T;
     __shared__ E s_cand[kCMax];
     __shared__ int32_t s_cnt[kWaves][64];
@@ -195,9 +195,10 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     __shared__ int s_nleaf, s_ovf, s_kmin, s_kmax, s_C, s_big, s_total;
     __shared__ unsigned long long s_base;
 
-    if (*dflag) return;
-    const int64_t ci = blockIdx.x;
     const Chunk ch = chunks[ci];
+    // The item's set: its root, and the base that makes indices set-local.
+    const int32_t root_code = __builtin_amdgcn_readfirstlane(sets[ch.set].root);
+    const int sbeg = __builtin_amdgcn_readfirstlane((int)sets[ch.set].beg);
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
 
@@ -351,7 +352,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     __syncthreads();
     if (s_ovf) {
         if (t == 0) {
-            cflag[ci] = 1;
+            blist[atomicAdd(&ctl->nbrute, 1u)] = ci;
             atomicAdd(&stats->brute, 1ull);
         }
         if (w == 0 && qv) soff[qidx] = -1;
@@ -385,7 +386,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     const int C = __builtin_amdgcn_readfirstlane(s_C);
     if (C > kCMax) {
         if (t == 0) {
-            cflag[ci] = 1;
+            blist[atomicAdd(&ctl->nbrute, 1u)] = ci;
             atomicAdd(&stats->brute, 1ull);
         }
         if (w == 0 && qv) soff[qidx] = -1;
@@ -407,7 +408,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         while (P2 < C) P2 <<= 1;
         if (P2 > kCMax) {
             if (t == 0) {
-                cflag[ci] = 1;
+                blist[atomicAdd(&ctl->nbrute, 1u)] = ci;
                 atomicAdd(&stats->brute, 1ull);
             }
             if (w == 0 && qv) soff[qidx] = -1;
@@ -581,7 +582,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         const int total = __shfl(inc, 63, 64);
         if (lane == 0) {
             s_total = total;
-            s_base = atomicAdd(cursor, (unsigned long long)total);
+            s_base = atomicAdd(&ctl->cursor, (unsigned long long)total);
             atomicAdd(&stats->pair_tests, (unsigned long long)C * (unsigned long long)ch.cnt);
             atomicAdd(&stats->candidates, (unsigned long long)C);
         }
@@ -590,9 +591,9 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     __syncthreads();
     const int64_t base = (int64_t)s_base;
     if (base + s_total > scap) {
-        // Scratch too small this time: counts are right, rows are redone
-        // after the host grows the scratch to the total it now knows.
-        if (t == 0) atomicOr(oflag, 1);
+        // Scratch too small this time: counts are right; the rows are redone
+        // once the scratch has grown to the need the cursor now holds.
+        if (t == 0) atomicOr(&ctl->overflow, kOvfScratch);
         if (w == 0 && qv) soff[qidx] = -2;
         return;
     }
@@ -611,24 +612,57 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                 while (word) {
                     const int j = __clz(word);
                     word &= ~(0x80000000u >> j);
-                    scratch[at++] = Ent<F32>::key(s_cand[kb + j]);
+                    scratch[at++] = Ent<F32>::key(s_cand[kb + j]) - sbeg;
                 }
             }
         }
     }
 }
 
+// The sweep: workgroup g takes work item g.  The grid is the host's bound on
+// the item count (exact after an eager build; a captured graph uses a bound
+// with a margin and reports an item count above it as an overflow).
+template <bool F32>
+__global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
+                                               const double4* __restrict__ pos,
+                                               const double4* __restrict__ orig,
+                                               const Node* __restrict__ nodes,
+                                               const int32_t* __restrict__ ctab,
+                                               const Leaf* __restrict__ leaves,
+                                               const int2* __restrict__ lrange,
+                                               const SetDev* __restrict__ sets,
+                                               const double* __restrict__ h,
+                                               int32_t* __restrict__ counts,
+                                               int64_t* __restrict__ soff,
+                                               int32_t* __restrict__ scratch, int64_t scap,
+                                               Ctl* __restrict__ ctl, int32_t* __restrict__ blist,
+                                               Stats* __restrict__ stats) {
+    if (ctl->data_bad) return;
+    const int nch = ctl->n_chunks;
+    const int ci = blockIdx.x;
+    if (ci == 0 && threadIdx.x == 0 && (unsigned)nch > gridDim.x)
+        atomicOr(&ctl->overflow, kOvfChunks);
+    if (ci >= nch) return;
+    sweep_item<F32>(ci, chunks, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
+                    scratch, scap, ctl, blist, stats);
+}
+
 // Rows from the scratch into the CSR array (original order, coalesced).  A
 // wavefront takes 64 consecutive rows; lane r first loads row r's length,
 // source and destination, then the wavefront copies the rows one by one with
-// those values broadcast from the owning lane.
+// those values broadcast from the owning lane.  Nothing is written when the
+// rows do not fit the caller's capacity.
 __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ counts,
                                                const int64_t* __restrict__ soff,
                                                const int64_t* __restrict__ offsets,
                                                const int32_t* __restrict__ scratch,
                                                int32_t* __restrict__ nbrs, int64_t n,
-                                               const int* __restrict__ dflag) {
-    if (*dflag) return;
+                                               int64_t capacity, Ctl* __restrict__ ctl) {
+    if (ctl->data_bad) return;
+    if (offsets[n] > capacity) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->overflow, kOvfCapacity);
+        return;
+    }
     const int lane = threadIdx.x & 63;
     const int64_t wid = ((int64_t)blockIdx.x * kWG + threadIdx.x) >> 6;
     const int64_t nw = ((int64_t)gridDim.x * kWG) >> 6;
@@ -644,7 +678,7 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
         const int rows = (int)min((int64_t)64, n - r0);
         for (int r = 0; r < rows; ++r) {
             const int64_t rso = __shfl(so, r, 64);
-            if (rso < 0) continue;
+            if (rso < 0) continue;  // exhaustive path, or no room in the scratch
             const int rc = __shfl(c, r, 64);
             const int64_t ro = __shfl(o, r, 64);
             for (int k = lane; k < rc; k += 64) nbrs[ro + k] = scratch[rso + k];
@@ -652,143 +686,197 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
     }
 }
 
-// Exhaustive path for flagged items: every j in original index order.
+// Exhaustive path for the listed items: every particle of the item's set in
+// original index order.  Persistent over the list.
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ chunks,
-                                               const int32_t* __restrict__ cflag,
+                                               const int32_t* __restrict__ blist,
+                                               const SetDev* __restrict__ sets,
                                                const double4* __restrict__ pos,
-                                               const double4* __restrict__ orig, int64_t n,
+                                               const double4* __restrict__ orig,
                                                const double* __restrict__ h,
                                                int32_t* __restrict__ counts,
-                                               const int64_t* __restrict__ offsets,
-                                               int32_t* __restrict__ nbrs,
-                                               const int* __restrict__ dflag) {
+                                               const int64_t* __restrict__ offsets, int64_t n,
+                                               int64_t capacity, int32_t* __restrict__ nbrs,
+                                               Ctl* __restrict__ ctl) {
     __shared__ int64_t sh[kWaves + 1];
-    const int64_t ci = blockIdx.x;
-    if (*dflag || !cflag[ci]) return;
-    const Chunk ch = chunks[ci];
+    if (ctl->data_bad) return;
+    if (MODE == kFill && offsets[n] > capacity) return;
+    const uint32_t nb = ctl->nbrute;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    for (int q = 0; q < ch.cnt; ++q) {
-        const double4 qp = pos[ch.beg + q];
-        const int qidx = (int)qp.w;
-        const double R = 2.0 * h[qidx];
-        int64_t run = MODE == kFill ? offsets[qidx] : 0;
-        const int64_t end = MODE == kFill ? offsets[qidx + 1] : 0;
-        int64_t mine = 0;
-        for (int64_t j0 = 0; j0 < n; j0 += kWG) {
-            const int64_t j = j0 + t;
-            bool acc = false;
-            if (j < n) {
-                const double4 o = orig[j];
-                acc = p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z);
+    for (uint32_t k = blockIdx.x; k < nb; k += gridDim.x) {
+        const Chunk ch = chunks[blist[k]];
+        const int64_t jb = sets[ch.set].beg, jn = sets[ch.set].n;
+        for (int q = 0; q < ch.cnt; ++q) {
+            const double4 qp = pos[ch.beg + q];
+            const int qidx = (int)qp.w;
+            const double R = 2.0 * h[qidx];
+            int64_t run = MODE == kFill ? offsets[qidx] : 0;
+            const int64_t end = MODE == kFill ? offsets[qidx + 1] : 0;
+            int64_t mine = 0;
+            for (int64_t j0 = 0; j0 < jn; j0 += kWG) {
+                const int64_t j = j0 + t;
+                bool acc = false;
+                if (j < jn) {
+                    const double4 o = orig[jb + j];
+                    acc = p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z);
+                }
+                if (MODE == kCount) {
+                    mine += acc;
+                } else {
+                    const uint64_t m = __ballot(acc);
+                    if (lane == 0) sh[w] = __popcll(m);
+                    __syncthreads();
+                    int64_t before = 0, tot = 0;
+                    for (int kk = 0; kk < kWaves; ++kk) {
+                        if (kk < w) before += sh[kk];
+                        tot += sh[kk];
+                    }
+                    const int64_t at = run + before + lanes_below(m);
+                    if (acc && at < end) nbrs[at] = (int32_t)j;
+                    run += tot;
+                    __syncthreads();
+                }
             }
             if (MODE == kCount) {
-                mine += acc;
-            } else {
-                const uint64_t m = __ballot(acc);
-                if (lane == 0) sh[w] = __popcll(m);
-                __syncthreads();
-                int64_t before = 0, tot = 0;
-                for (int k = 0; k < kWaves; ++k) {
-                    if (k < w) before += sh[k];
-                    tot += sh[k];
-                }
-                const int64_t at = run + before + lanes_below(m);
-                if (acc && at < end) nbrs[at] = (int32_t)j;
-                run += tot;
-                __syncthreads();
+                const int64_t tot = block_sum<kWG>(mine, sh);
+                if (t == 0) counts[qidx] = (int32_t)tot;
             }
-        }
-        if (MODE == kCount) {
-            int64_t tot = block_sum<kWG>(mine, sh);
-            if (t == 0) counts[qidx] = (int32_t)tot;
         }
     }
 }
 
-__global__ void k_check_h(const double* __restrict__ h, int64_t n, int* __restrict__ dflag) {
+// Clears the search's part of the control block and the search counters.
+__global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
+    if (threadIdx.x == 0) {
+        ctl->queue = 0;
+        ctl->nbrute = 0;
+        ctl->cursor = 0;
+        ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
+        ctl->overflow &= ~(kOvfScratch | kOvfCapacity | kOvfChunks);
+        stats->pair_tests = 0;
+        stats->confirms = 0;
+        stats->brute = 0;
+        stats->candidates = 0;
+    }
+}
+
+__global__ void k_check_h(const double* __restrict__ h, int64_t n, Ctl* __restrict__ ctl) {
     bool bad = false;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         double v = h[i];
         bad |= !(v >= 0.0 && isfinite(v));
     }
-    if (__ballot(bad) && lane_id() == 0) atomicOr(dflag, 1);
+    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->data_bad, 2);
 }
 
+// Lists per set: totals[k] = offsets[end of set k] - offsets[start of set k].
+__global__ void k_set_totals(const int64_t* __restrict__ offsets, const SetDev* __restrict__ sets,
+                             int nsets, int64_t* __restrict__ totals) {
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nsets; k += gridDim.x * blockDim.x)
+        totals[k] = offsets[sets[k].beg + sets[k].n] - offsets[sets[k].beg];
+}
+
+constexpr unsigned kBruteGrid = 512;
+
 template <bool F32>
-void launch_sweep(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
+void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipStream_t st) {
     t.timer.start(kPhSweep, st);
-    hipLaunchKernelGGL((k_sweep<F32>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
-                       t.chunks.as<Chunk>(), t.pos.as<double4>(), t.orig.as<double4>(),
-                       t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
-                       t.lrange.as<int2>(), t.root_code, h, counts, t.soff.as<int64_t>(),
-                       t.scratch.as<int32_t>(), t.scap, t.scal.as<unsigned long long>(),
-                       t.cflag.as<int32_t>(), t.flag.as<int>() + 1, t.flag.as<int>(),
+    hipLaunchKernelGGL((k_sweep<F32>), dim3(grid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
+                       t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
+                       t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
+                       t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
+                       t.scratch.as<int32_t>(), t.scap, t.ctl.as<Ctl>(), t.blist.as<int32_t>(),
                        t.stats.as<Stats>());
     BT_LAUNCH();
     t.timer.stop(kPhSweep, st);
-    hipLaunchKernelGGL((k_brute<kCount>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
-                       t.chunks.as<Chunk>(), t.cflag.as<int32_t>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), t.n, h, counts, nullptr, nullptr, t.flag.as<int>());
+    hipLaunchKernelGGL((k_brute<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
+                       t.blist.as<int32_t>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
+                       t.orig.as<double4>(), h, counts, nullptr, t.n, (int64_t)0, nullptr,
+                       t.ctl.as<Ctl>());
+    BT_LAUNCH();
+}
+
+// Pass 1 queued: counts, rows into the scratch, offsets.
+void queue_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, unsigned grid,
+                 hipStream_t st) {
+    const bool f32 = t.prm.precision == BTREE_FP32_FILTER;
+    hipLaunchKernelGGL(k_find_reset, dim3(1), dim3(64), 0, st, t.ctl.as<Ctl>(), t.stats.as<Stats>());
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
+                       st, h, t.n, t.ctl.as<Ctl>());
+    BT_LAUNCH();
+    if (f32) launch_sweep<true>(t, h, counts, grid, st);
+    else launch_sweep<false>(t, h, counts, grid, st);
+    scan_exclusive_i32(counts, offsets, t.n, t, st, &t.ctl.as<Ctl>()->data_bad);
+}
+
+// Pass 2 queued: rows from the scratch, then the exhaustive rows.
+void queue_pass2(Tree& t, const double* h, const int32_t* counts, const int64_t* offsets,
+                 int32_t* nbrs, int64_t capacity, hipStream_t st) {
+    t.timer.start(kPhPlace, st);
+    const int64_t waves = (t.n + 63) / 64;
+    unsigned grid = grid_for(waves < 1 ? 1 : waves, kWG / 64);
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_place, dim3(grid), dim3(kWG), 0, st, counts, t.soff.as<int64_t>(), offsets,
+                       t.scratch.as<int32_t>(), nbrs, t.n, capacity, t.ctl.as<Ctl>());
+    BT_LAUNCH();
+    t.timer.stop(kPhPlace, st);
+    hipLaunchKernelGGL((k_brute<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
+                       t.blist.as<int32_t>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
+                       t.orig.as<double4>(), h, nullptr, offsets, t.n, capacity, nbrs,
+                       t.ctl.as<Ctl>());
     BT_LAUNCH();
 }
 
 }  // namespace
 
-int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
-    const bool f32 = t.prm.precision == BTREE_FP32_FILTER;
-    t.scal.reserve(64);
-    t.soff.reserve(sizeof(int64_t) * t.n);
-    if (t.scap == 0) {
-        t.scap = std::max<int64_t>(t.n * 128, 1 << 20);
-        t.scratch.reserve(sizeof(int32_t) * t.scap);
+void find_reserve(Tree& t, int64_t entries) {
+    t.soff.reserve(sizeof(int64_t) * std::max<int64_t>(t.n, 1));
+    if (entries > t.scap) {
+        t.scratch.release();
+        t.scap = 0;
+        t.scratch.reserve(sizeof(int32_t) * entries);
+        t.scap = entries;
     }
-    BT_HIP(hipMemsetAsync(&t.stats.as<Stats>()->pair_tests, 0, 4 * sizeof(unsigned long long), st));
-    BT_HIP(hipMemsetAsync(t.flag.p, 0, 2 * sizeof(int32_t), st));
-    hipLaunchKernelGGL(k_check_h, dim3(grid_for(t.n, 256) < 2048 ? grid_for(t.n, 256) : 2048),
-                       dim3(256), 0, st, h, t.n, t.flag.as<int>());
-    BT_LAUNCH();
+}
+
+int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
+    if (t.scap == 0) find_reserve(t, std::max<int64_t>(t.n * 128, 1 << 20));
+    else find_reserve(t, t.scap);
+    const unsigned grid = (unsigned)std::max<int64_t>(1, t.n_chunks);
     int64_t total = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        BT_HIP(hipMemsetAsync(t.cflag.p, 0, sizeof(int32_t) * t.n_chunks, st));
-        BT_HIP(hipMemsetAsync(t.scal.p, 0, sizeof(unsigned long long), st));
-        BT_HIP(hipMemsetAsync(t.flag.as<int>() + 1, 0, sizeof(int32_t), st));
-        if (f32) launch_sweep<true>(t, h, counts, st);
-        else launch_sweep<false>(t, h, counts, st);
-        scan_exclusive_i32(counts, offsets, t.n, t, st, t.flag.as<int>());
-        int flags[2] = {0, 0};
-        unsigned long long need = 0;
+        queue_pass1(t, h, counts, offsets, grid, st);
         BT_HIP(hipMemcpyAsync(&total, offsets + t.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
-        BT_HIP(hipMemcpyAsync(flags, t.flag.p, sizeof flags, hipMemcpyDeviceToHost, st));
-        BT_HIP(hipMemcpyAsync(&need, t.scal.p, sizeof need, hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
         BT_HIP(hipStreamSynchronize(st));
-        if (flags[0]) fail(BTREE_EINVAL, "btree_find_neighbors: h must be finite and >= 0");
-        if (!flags[1]) break;
+        if (t.host_ctl.data_bad & 2) fail(BTREE_EINVAL, "btree_find_neighbors: h must be finite and >= 0");
+        if (t.host_ctl.overflow & kOvfChunks) fail(BTREE_EDEVICE, "btree_find_neighbors: work items out of date");
+        if (!(t.host_ctl.overflow & kOvfScratch)) break;
         if (attempt == 1) fail(BTREE_EDEVICE, "btree_find_neighbors: scratch sizing failed");
         // Rows did not fit: grow the scratch to the exact need and sweep again.
-        t.scap = (int64_t)need + (int64_t)need / 16 + 1024;
-        t.scratch.release();
-        t.scratch.reserve(sizeof(int32_t) * t.scap);
-        BT_HIP(hipMemsetAsync(&t.stats.as<Stats>()->pair_tests, 0, 4 * sizeof(unsigned long long), st));
+        const int64_t need = (int64_t)t.host_ctl.cursor;
+        find_reserve(t, need + need / 16 + 1024);
     }
     return total;
 }
 
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs, hipStream_t st) {
-    t.timer.start(kPhPlace, st);
-    const int64_t waves = (t.n + 63) / 64;
-    unsigned grid = grid_for(waves < 1 ? 1 : waves, kWG / 64);
-    if (grid > 8192) grid = 8192;
-    hipLaunchKernelGGL(k_place, dim3(grid), dim3(kWG), 0, st, t.p1_counts, t.soff.as<int64_t>(),
-                       offsets, t.scratch.as<int32_t>(), nbrs, t.n, t.flag.as<int>());
-    BT_LAUNCH();
-    t.timer.stop(kPhPlace, st);
-    hipLaunchKernelGGL((k_brute<kFill>), dim3((unsigned)t.n_chunks), dim3(kWG), 0, st,
-                       t.chunks.as<Chunk>(), t.cflag.as<int32_t>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), t.n, h, nullptr, offsets, nbrs, t.flag.as<int>());
-    BT_LAUNCH();
+    queue_pass2(t, h, t.p1_counts, offsets, nbrs, INT64_MAX, st);
+}
+
+void find_queue(Tree& t, const double* h, int32_t* counts, int64_t* offsets, int32_t* nbrs,
+                int64_t capacity, int64_t* totals, hipStream_t st) {
+    queue_pass1(t, h, counts, offsets, (unsigned)std::max<int64_t>(1, t.chunk_cap), st);
+    queue_pass2(t, h, counts, offsets, nbrs, capacity, st);
+    if (totals) {
+        hipLaunchKernelGGL(k_set_totals, dim3(grid_for(t.nsets, 256)), dim3(256), 0, st, offsets,
+                           t.sets.as<SetDev>(), t.nsets, totals);
+        BT_LAUNCH();
+    }
 }
 
 }  // namespace bt
