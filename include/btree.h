@@ -171,6 +171,62 @@ btree_status btree_export(btree_handle t, int32_t* leaf_beg, int32_t* leaf_cnt,
  * Waits for work the handle queued to finish first. */
 btree_status btree_destroy(btree_handle t);
 
+/* ------------------------------------------------------------------------
+ * Batched form: many independent particle sets, each with its own b-tree
+ * (Algorithm 1) and its own neighbour lists (Algorithm 2), built and
+ * searched together by one captured HIP graph per call.
+ * ---------------------------------------------------------------------- */
+typedef struct btree_batch* btree_batch_handle;
+
+/* Plans a batch of nsets sets (1 <= nsets <= 2^20).  set_offsets: HOST
+ * int64[nsets+1], set_offsets[0] = 0, non-decreasing, total below 2^31; set
+ * k is particles [set_offsets[k], set_offsets[k+1]) of the concatenated
+ * arrays (empty sets allowed).  per_set: HOST btree_params[nsets] (NULL =
+ * defaults for every set); s, alpha, beta and max_depth may differ between
+ * sets, precision must not, timing must be 0.  Allocates the device pools
+ * of the batch; queues nothing.  Errors: EINVAL, ENOMEM, EDEVICE. */
+btree_status btree_batch_create(int32_t nsets, const int64_t* set_offsets,
+                                const btree_params* per_set,
+                                btree_batch_handle* out);
+
+/* BuildTree and FindNeighbors of every set of the batch.
+ * x, y, z, h: device FP64[n_total], the sets concatenated.
+ * counts: device int32[n_total]; offsets: device int64[n_total+1]; one CSR
+ *   over all sets (offsets[0] = 0).  Rows of set k are rows set_offsets[k]
+ *   .. set_offsets[k+1]-1; their entries are indices LOCAL to set k (0 is
+ *   the set's first particle), ascending; each set's lists follow the
+ *   previous set's.  Results per set are identical to btree_build +
+ *   btree_find_neighbors on that set alone with the same parameters.
+ * nbrs: device int32[capacity] (may be NULL when capacity = 0).
+ * totals: HOST int64[nsets] or NULL, entries per set; total: HOST int64,
+ *   their sum.
+ * The work is one graph launch on hip_stream, recorded on the first call
+ * with a given set of pointers and capacity and replayed on later calls
+ * with the same ones.  The first call on a handle first runs an eager build
+ * and count pass to size the pools.  The call waits for the stream.  When
+ * a pool proves too small for new data, the handle grows it, records the
+ * graph again and repeats the run.
+ * Errors: EINVAL (NULL arrays with n_total > 0, capacity < 0, non-finite
+ * coordinate, h < 0 or non-finite: then no caller output is written),
+ * EOVERFLOW (capacity < total: counts, offsets, totals and *total are
+ * written, nbrs is not), ESTATE (NULL handle), ENOMEM, EDEVICE. */
+btree_status btree_batch_run(btree_batch_handle b, const double* x,
+                             const double* y, const double* z,
+                             const double* h, int32_t* counts,
+                             int64_t* offsets, int32_t* nbrs,
+                             int64_t capacity, int64_t* totals,
+                             int64_t* total, void* hip_stream);
+
+/* Shape of the batch's forest and counters of its last run, summed over
+ * the sets (depth and max_leaf: maxima).  phase_ms is zero; phase_calls[0]
+ * counts graph launches and phase_calls[1] graph recordings.
+ * Errors: EINVAL (NULL argument). */
+btree_status btree_batch_stats(btree_batch_handle b, btree_stats_t* out);
+
+/* Releases the batch and its device memory (NULL is a no-op); waits for
+ * the device first. */
+btree_status btree_batch_destroy(btree_batch_handle b);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char* btree_last_error(void);
 

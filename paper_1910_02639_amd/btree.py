@@ -28,7 +28,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFL
                 -5: "ESTATE"}
 
 SYMBOLS = ["btree_params_default", "btree_build", "btree_rebuild", "btree_find_neighbors",
-           "btree_stats", "btree_export", "btree_destroy", "btree_last_error"]
+           "btree_stats", "btree_export", "btree_destroy", "btree_last_error",
+           "btree_batch_create", "btree_batch_run", "btree_batch_stats", "btree_batch_destroy"]
 
 
 class Params(ctypes.Structure):
@@ -85,6 +86,15 @@ def lib():
         L.btree_destroy.argtypes = [P]
         L.btree_last_error.restype = ctypes.c_char_p
         L.btree_last_error.argtypes = []
+        L.btree_batch_create.restype = ctypes.c_int
+        L.btree_batch_create.argtypes = [ctypes.c_int32, P, ctypes.POINTER(Params),
+                                         ctypes.POINTER(P)]
+        L.btree_batch_run.restype = ctypes.c_int
+        L.btree_batch_run.argtypes = [P, P, P, P, P, P, P, P, I64, P, ctypes.POINTER(I64), P]
+        L.btree_batch_stats.restype = ctypes.c_int
+        L.btree_batch_stats.argtypes = [P, ctypes.POINTER(Stats)]
+        L.btree_batch_destroy.restype = ctypes.c_int
+        L.btree_batch_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -242,6 +252,108 @@ class BTree:
                                   order.ctypes.data, _stream(stream)))
         return {"leaf_beg": beg[:nl], "leaf_cnt": cnt[:nl], "leaf_depth": dep[:nl],
                 "order": order[:self.n]}
+
+
+def _stats_dict(s: Stats) -> dict:
+    d = {k: getattr(s, k) for k, _ in Stats._fields_
+         if k not in ("b_hist", "phase_ms", "phase_calls")}
+    d["b_hist"] = {b: int(c) for b, c in enumerate(s.b_hist) if c}
+    return d
+
+
+class Batch:
+    """Many independent particle sets built and searched by one captured
+    HIP graph per run (btree_batch_*).  `set_sizes` gives the particles of
+    each set; arrays passed to run() hold the sets concatenated."""
+
+    def __init__(self, set_sizes, params_per_set=None, precision="fp32", **kw):
+        sizes = np.asarray(set_sizes, dtype=np.int64)
+        if sizes.ndim != 1 or len(sizes) < 1 or (sizes < 0).any():
+            raise ValueError("set_sizes must be a non-empty list of sizes >= 0")
+        self.nsets = int(len(sizes))
+        self.set_offsets = np.zeros(self.nsets + 1, dtype=np.int64)
+        np.cumsum(sizes, out=self.set_offsets[1:])
+        self.n = int(self.set_offsets[-1])
+        if params_per_set is None:
+            params_per_set = [dict(kw)] * self.nsets
+        if len(params_per_set) != self.nsets:
+            raise ValueError("params_per_set needs one entry per set")
+        arr = (Params * self.nsets)()
+        for k, d in enumerate(params_per_set):
+            d = dict(d)
+            d.setdefault("precision", precision)
+            arr[k] = params(**d)
+        self._params = arr
+        h = ctypes.c_void_p()
+        _check(lib().btree_batch_create(self.nsets, self.set_offsets.ctypes.data, arr,
+                                        ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().btree_batch_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def run(self, x, y, z, h, counts, offsets, nbrs, stream=None):
+        """One batched run into caller buffers; returns (totals per set as
+        numpy int64, total).  Raises BTreeError (status EOVERFLOW) when nbrs
+        is too small; counts and offsets are then valid."""
+        for a, nm in ((x, "x"), (y, "y"), (z, "z"), (h, "h")):
+            _dev_f64(a, nm)
+            if a.shape[0] != self.n:
+                raise ValueError("%s must have %d entries" % (nm, self.n))
+        totals = np.zeros(self.nsets, dtype=np.int64)
+        total = ctypes.c_int64()
+        st = lib().btree_batch_run(self._h, ctypes.c_void_p(x.data_ptr()),
+                                   ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(z.data_ptr()),
+                                   ctypes.c_void_p(h.data_ptr()),
+                                   ctypes.c_void_p(counts.data_ptr()),
+                                   ctypes.c_void_p(offsets.data_ptr()),
+                                   ctypes.c_void_p(nbrs.data_ptr()), int(nbrs.numel()),
+                                   totals.ctypes.data, ctypes.byref(total), _stream(stream))
+        self.last_totals = totals
+        self.last_total = int(total.value)
+        _check(st)
+        return totals, int(total.value)
+
+    def find(self, x, y, z, h, stream=None):
+        """Batched FindNeighbors with outputs allocated here: (counts,
+        offsets, nbrs, totals).  Rows of set k are rows set_offsets[k]..;
+        their indices are local to set k."""
+        import torch
+        dev = x.device
+        counts = torch.empty(max(self.n, 1), dtype=torch.int32, device=dev)
+        offsets = torch.empty(self.n + 1, dtype=torch.int64, device=dev)
+        nbrs = torch.empty(max(getattr(self, "_cap", 1), 1), dtype=torch.int32, device=dev)
+        try:
+            totals, total = self.run(x, y, z, h, counts, offsets, nbrs, stream)
+        except BTreeError as e:
+            if e.status != BTREE_EOVERFLOW:
+                raise
+            self._cap = self.last_total + self.last_total // 8 + 1024
+            nbrs = torch.empty(self._cap, dtype=torch.int32, device=dev)
+            totals, total = self.run(x, y, z, h, counts, offsets, nbrs, stream)
+        return counts[:self.n], offsets, nbrs[:total], totals
+
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().btree_batch_stats(self._h, ctypes.byref(s)))
+        d = _stats_dict(s)
+        d["graph_launches"] = int(s.phase_calls[0])
+        d["graph_captures"] = int(s.phase_calls[1])
+        return d
 
 
 def find_neighbors(x, y, z, h, bucket_size=64, alpha=0.5, beta=0.5, max_depth=32,

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libbtree.so")
-SOURCES = ["scan.hip", "sort.hip", "build.hip", "find.hip", "api.hip"]
+SOURCES = ["scan.hip", "sort.hip", "build.hip", "find.hip", "api.hip", "batch.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

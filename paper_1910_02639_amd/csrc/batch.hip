@@ -1,0 +1,284 @@
+// Batched form: many independent particle sets built and searched by one
+// captured HIP graph.  The sets share one control block, one set of pools
+// and one launch sequence (set id in the top bits of the Morton key, per-set
+// roots, work items tagged with their set), so the whole batch costs the
+// launches of a single tree.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.h"
+
+namespace bt {
+
+struct Batch {
+    Tree t;
+    hipStream_t cs = nullptr;       // private stream the graph is captured on
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void* key[7] = {};        // caller pointers baked into the graph
+    int64_t key_cap = -1;
+    bool primed = false;            // an eager run has sized the pools
+    int64_t launches = 0;
+    int64_t captures = 0;
+    std::vector<int64_t> host_tot;  // per-set totals of the last run
+
+    void drop_graph() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~Batch() {
+        drop_graph();
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+};
+
+namespace {
+
+void check_set_params(const btree_params& p, const btree_params& p0) {
+    if (p.bucket_size < 1) fail(BTREE_EINVAL, "bucket_size must be >= 1");
+    if (!std::isfinite(p.alpha) || p.alpha < 0.0) fail(BTREE_EINVAL, "alpha must be finite and >= 0");
+    if (!std::isfinite(p.beta)) fail(BTREE_EINVAL, "beta must be finite");
+    if (p.max_depth < 0 || p.max_depth > 64) fail(BTREE_EINVAL, "max_depth must be in [0, 64]");
+    if (p.precision != BTREE_FP64 && p.precision != BTREE_FP32_FILTER)
+        fail(BTREE_EINVAL, "precision must be BTREE_FP64 or BTREE_FP32_FILTER");
+    if (p.precision != p0.precision) fail(BTREE_EINVAL, "all sets of a batch need one precision");
+    if (p.group_size != 0 && p.group_size != kGroup) fail(BTREE_EINVAL, "group_size must be 0 or 64");
+    if (p.timing != 0) fail(BTREE_EINVAL, "timing is not available in a batch (use 0)");
+    for (int k = 0; k < 5; ++k)
+        if (p.reserved[k] != 0) fail(BTREE_EINVAL, "reserved fields must be zero");
+}
+
+__global__ void k_zero_offsets(int64_t* __restrict__ offsets) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) offsets[0] = 0;
+}
+
+// Records build + search of every set into a graph on the private stream.
+void capture(Batch& B, const double* x, const double* y, const double* z, const double* h,
+             int32_t* counts, int64_t* offsets, int32_t* nbrs, int64_t capacity) {
+    Tree& t = B.t;
+    B.drop_graph();
+    BT_HIP(hipStreamBeginCapture(B.cs, hipStreamCaptureModeThreadLocal));
+    try {
+        build_queue(t, x, y, z, (int)t.level_cap, false, B.cs);
+        find_queue(t, h, counts, offsets, nbrs, capacity, t.tot.as<int64_t>(), B.cs);
+    } catch (...) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(B.cs, &g);
+        if (g) (void)hipGraphDestroy(g);
+        throw;
+    }
+    BT_HIP(hipStreamEndCapture(B.cs, &B.graph));
+    BT_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    const void* k[7] = {x, y, z, h, counts, offsets, nbrs};
+    std::memcpy(B.key, k, sizeof k);
+    B.key_cap = capacity;
+    ++B.captures;
+}
+
+bool same_key(const Batch& B, const double* x, const double* y, const double* z, const double* h,
+              const int32_t* counts, const int64_t* offsets, const int32_t* nbrs, int64_t cap) {
+    const void* k[7] = {x, y, z, h, counts, offsets, nbrs};
+    return B.exec && std::memcmp(B.key, k, sizeof k) == 0 && B.key_cap == cap;
+}
+
+// First run: an eager build and count pass size the level count, the work
+// item bound and the scratch for this batch.
+void prime(Batch& B, const double* x, const double* y, const double* z, const double* h,
+           int32_t* counts, int64_t* offsets, hipStream_t st) {
+    Tree& t = B.t;
+    build_tree(t, x, y, z, st);
+    t.level_cap = std::max<int64_t>(1, std::min<int64_t>(t.levels_seen + 1, 66));
+    t.chunk_cap = t.n_chunks + t.n_chunks / 4 + 64;
+    (void)find_pass1(t, h, counts, offsets, st);
+    B.primed = true;
+}
+
+}  // namespace
+
+}  // namespace bt
+
+struct btree_batch {
+    bt::Batch b;
+};
+
+using namespace bt;
+
+template <class F>
+static btree_status guarded_b(F&& f) {
+    try {
+        f();
+        return BTREE_OK;
+    } catch (const Fail& e) {
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return BTREE_ENOMEM;
+    } catch (...) {
+        set_error("unexpected internal error");
+        return BTREE_EDEVICE;
+    }
+}
+
+extern "C" {
+
+btree_status btree_batch_create(int32_t nsets, const int64_t* set_offsets,
+                                const btree_params* per_set, btree_batch_handle* out) {
+    return guarded_b([&] {
+        if (!out) fail(BTREE_EINVAL, "btree_batch_create: out is NULL");
+        *out = nullptr;
+        if (nsets < 1 || nsets > (1 << 20)) fail(BTREE_EINVAL, "btree_batch_create: nsets must be in [1, 2^20]");
+        if (!set_offsets) fail(BTREE_EINVAL, "btree_batch_create: set_offsets is NULL");
+        if (set_offsets[0] != 0) fail(BTREE_EINVAL, "btree_batch_create: set_offsets[0] must be 0");
+        for (int k = 0; k < nsets; ++k)
+            if (set_offsets[k + 1] < set_offsets[k])
+                fail(BTREE_EINVAL, "btree_batch_create: set_offsets must be non-decreasing");
+        if (set_offsets[nsets] >= 0x7fffffffll)
+            fail(BTREE_EINVAL, "btree_batch_create: total particles must be below 2^31");
+        std::vector<btree_params> prm((size_t)nsets);
+        for (int k = 0; k < nsets; ++k) {
+            if (per_set) prm[k] = per_set[k];
+            else btree_params_default(&prm[k]);
+        }
+        for (int k = 0; k < nsets; ++k) {
+            check_set_params(prm[k], prm[0]);
+            const int64_t nk = set_offsets[k + 1] - set_offsets[k];
+            if ((nk + prm[k].bucket_size - 1) / prm[k].bucket_size > (1ll << 30))
+                fail(BTREE_EINVAL, "btree_batch_create: n / bucket_size must not exceed 2^30");
+        }
+        btree_batch* H = new btree_batch();
+        Batch& B = H->b;
+        Tree& t = B.t;
+        try {
+            t.prm = prm[0];
+            t.timer.on = false;
+            if (hipGetDevice(&t.device) != hipSuccess) t.device = 0;
+            BT_HIP(hipStreamCreateWithFlags(&B.cs, hipStreamNonBlocking));
+            plan_sets(t, nsets, set_offsets, prm.data());
+            t.level_cap = 66;
+            B.host_tot.assign((size_t)nsets, 0);
+        } catch (...) {
+            delete H;
+            throw;
+        }
+        *out = H;
+        set_error("");
+    });
+}
+
+btree_status btree_batch_run(btree_batch_handle H, const double* x, const double* y,
+                             const double* z, const double* h, int32_t* counts, int64_t* offsets,
+                             int32_t* nbrs, int64_t capacity, int64_t* totals, int64_t* total,
+                             void* hip_stream) {
+    return guarded_b([&] {
+        if (!H) fail(BTREE_ESTATE, "btree_batch_run: NULL handle");
+        Batch& B = H->b;
+        Tree& t = B.t;
+        const int64_t n = t.n;
+        if (!total) fail(BTREE_EINVAL, "btree_batch_run: total is NULL");
+        if (!offsets) fail(BTREE_EINVAL, "btree_batch_run: offsets is NULL");
+        if (n > 0 && (!x || !y || !z || !h || !counts))
+            fail(BTREE_EINVAL, "btree_batch_run: NULL particle or counts array");
+        if (capacity < 0) fail(BTREE_EINVAL, "btree_batch_run: capacity < 0");
+        if (capacity > 0 && !nbrs) fail(BTREE_EINVAL, "btree_batch_run: nbrs is NULL with capacity > 0");
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        *total = 0;
+        if (n == 0) {
+            hipLaunchKernelGGL(k_zero_offsets, dim3(1), dim3(64), 0, st, offsets);
+            BT_LAUNCH();
+            BT_HIP(hipStreamSynchronize(st));
+            if (totals)
+                for (int k = 0; k < t.nsets; ++k) totals[k] = 0;
+            set_error("");
+            return;
+        }
+        if (!B.primed) prime(B, x, y, z, h, counts, offsets, st);
+        for (int attempt = 0;; ++attempt) {
+            if (!same_key(B, x, y, z, h, counts, offsets, nbrs, capacity))
+                capture(B, x, y, z, h, counts, offsets, nbrs, capacity);
+            BT_HIP(hipGraphLaunch(B.exec, st));
+            ++B.launches;
+            BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+            BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
+            BT_HIP(hipMemcpyAsync(B.host_tot.data(), t.tot.p, sizeof(int64_t) * t.nsets,
+                                  hipMemcpyDeviceToHost, st));
+            BT_HIP(hipStreamSynchronize(st));
+            const Ctl& c = t.host_ctl;
+            if (c.data_bad & 1) fail(BTREE_EINVAL, "btree_batch_run: non-finite particle coordinate");
+            if (c.data_bad & 2) fail(BTREE_EINVAL, "btree_batch_run: h must be finite and >= 0");
+            const int ovf = c.overflow & ~kOvfCapacity;
+            if (!ovf) break;
+            if (attempt >= 8) fail(BTREE_ENOMEM, "btree_batch_run: pools kept overflowing");
+            // Grow what was too small, then capture again.
+            if (ovf & (kOvfNodes | kOvfCtab | kOvfHist)) {
+                if (ovf & kOvfNodes) t.node_cap *= 2;
+                if (ovf & kOvfCtab) t.ctab_cap *= 2;
+                if (ovf & kOvfHist) t.hist_cap *= 2;
+                plan_sets(t, t.nsets, t.set_off.data(), t.set_prm.data());
+            }
+            if (ovf & kOvfLevels) t.level_cap = std::min<int64_t>(66, 2 * t.level_cap + 1);
+            if (ovf & kOvfChunks) t.chunk_cap = (int64_t)c.n_chunks + c.n_chunks / 4 + 64;
+            if (ovf & kOvfScratch) find_reserve(t, (int64_t)c.cursor + (int64_t)(c.cursor / 16) + 1024);
+            B.drop_graph();
+        }
+        const Ctl& c = t.host_ctl;
+        t.n_internal = c.n_nodes;
+        t.n_leaves = c.n_leaves;
+        t.n_chunks = c.n_chunks;
+        t.ctab_len = c.ct_len;
+        t.depth = c.depth;
+        t.max_leaf = c.max_leaf;
+        t.oversized = c.oversized;
+        t.levels_seen = c.levels;
+        int64_t sum = 0;
+        for (int k = 0; k < t.nsets; ++k) {
+            sum += B.host_tot[k];
+            if (totals) totals[k] = B.host_tot[k];
+        }
+        *total = sum;
+        t.last_total = sum;
+        if (c.overflow & kOvfCapacity)
+            fail(BTREE_EOVERFLOW, "btree_batch_run: capacity " + std::to_string(capacity) +
+                                      " < total " + std::to_string(sum));
+        set_error("");
+    });
+}
+
+btree_status btree_batch_stats(btree_batch_handle H, btree_stats_t* out) {
+    if (!H || !out) {
+        set_error("btree_batch_stats: NULL argument");
+        return BTREE_EINVAL;
+    }
+    const Batch& B = H->b;
+    const Tree& t = B.t;
+    std::memset(out, 0, sizeof *out);
+    out->n = t.n;
+    out->n_internal = t.n_internal;
+    out->n_leaves = t.n_leaves;
+    out->depth = t.depth;
+    out->rounds = (int64_t)t.host_stats.rounds;
+    out->max_leaf = t.max_leaf;
+    out->oversized = t.oversized;
+    out->n_chunks = t.n_chunks;
+    for (int k = 0; k < 65; ++k) out->b_hist[k] = (int64_t)t.host_stats.b_hist[k];
+    out->total = t.last_total;
+    out->pair_tests = (int64_t)t.host_stats.pair_tests;
+    out->fp64_confirms = (int64_t)t.host_stats.confirms;
+    out->brute_chunks = (int64_t)t.host_stats.brute;
+    out->candidates = (int64_t)t.host_stats.candidates;
+    out->phase_calls[0] = B.launches;
+    out->phase_calls[1] = B.captures;
+    set_error("");
+    return BTREE_OK;
+}
+
+btree_status btree_batch_destroy(btree_batch_handle H) {
+    if (!H) return BTREE_OK;
+    (void)hipDeviceSynchronize();
+    delete H;
+    return BTREE_OK;
+}
+
+}  // extern "C"

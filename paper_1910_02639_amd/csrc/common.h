@@ -161,6 +161,10 @@ constexpr int64_t kTileN = 8192;
 // Overflow bits of Ctl::overflow (a pool was too small for this input).
 enum { kOvfNodes = 1, kOvfLeaves = 2, kOvfCtab = 4, kOvfHist = 8, kOvfLevels = 16,
        kOvfScratch = 32, kOvfCapacity = 64, kOvfChunks = 128 };
+// A build that overflowed a pool left an incomplete tree: the search must
+// not walk it.  Work items beyond the launched grid leave counts unset: the
+// lists must not be placed.
+constexpr int kOvfTree = kOvfNodes | kOvfLeaves | kOvfCtab | kOvfHist | kOvfLevels;
 
 // Device control block of a build and its search: every level reads its
 // cell range from here, so no host round trip is needed between launches.

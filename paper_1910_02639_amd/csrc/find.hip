@@ -637,7 +637,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                int32_t* __restrict__ scratch, int64_t scap,
                                                Ctl* __restrict__ ctl, int32_t* __restrict__ blist,
                                                Stats* __restrict__ stats) {
-    if (ctl->data_bad) return;
+    if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     const int nch = ctl->n_chunks;
     const int ci = blockIdx.x;
     if (ci == 0 && threadIdx.x == 0 && (unsigned)nch > gridDim.x)
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
                                                const int32_t* __restrict__ scratch,
                                                int32_t* __restrict__ nbrs, int64_t n,
                                                int64_t capacity, Ctl* __restrict__ ctl) {
-    if (ctl->data_bad) return;
+    if (ctl->data_bad || (ctl->overflow & (kOvfTree | kOvfChunks))) return;
     if (offsets[n] > capacity) {
         if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&ctl->overflow, kOvfCapacity);
         return;
@@ -700,8 +700,8 @@ __global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ chunks,
                                                int64_t capacity, int32_t* __restrict__ nbrs,
                                                Ctl* __restrict__ ctl) {
     __shared__ int64_t sh[kWaves + 1];
-    if (ctl->data_bad) return;
-    if (MODE == kFill && offsets[n] > capacity) return;
+    if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
+    if (MODE == kFill && ((ctl->overflow & kOvfChunks) || offsets[n] > capacity)) return;
     const uint32_t nb = ctl->nbrute;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (uint32_t k = blockIdx.x; k < nb; k += gridDim.x) {
