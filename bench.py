@@ -1,11 +1,18 @@
 #!/usr/bin/env python3
-"""Benchmark of the b-tree hot path on one MI355X.
+"""Benchmark of the b-tree hot path (BuildTree + FindNeighbors) on one MI355X.
 
-One step = BuildTree (btree_rebuild) + FindNeighbors pass 1 (counts,
-offsets) + pass 2 (CSR lists) over the workload, inputs resident in HBM.
-Prints one JSON line.  `value` is particles per second of whole steps.
+Default workload Batch64: 64 independent particle sets, sizes log-uniform in
+[1e4, 1e6], even sets uniform cubes and odd sets Plummer spheres.  One step
+is one batched run: BuildTree and both FindNeighbors passes of every set as
+one captured HIP graph (FP32 filter + FP64 band), parameters per set from
+the autotuner's cache.  Compared in the same run with the plain FP64 form
+launched one set at a time (and the FP32 form one set at a time), with the
+8M-particle Plummer sphere (P8M) as a single-set block, and with the FP64
+oracle on the host cores.  Inputs are resident in HBM before timing.
 
-  python bench.py [--steps K] [--warmup W] [--workload P8M] [--precision fp32]
+  python bench.py [--steps K] [--warmup W] [--workload Batch64|P8M|...]
+
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -21,12 +28,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# Non-packed FP32 VALU: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s.
+# Non-packed VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 # VALU lane-ops of one FP32-filter pair test: 3 sub, 1 mul, 2 fma, 2 compare.
 OPS_PER_TEST_F32 = 8
 # ... and of one FP64 pair test: 3 sub, 3 mul, 2 add, 1 compare.
 OPS_PER_TEST_F64 = 9
+METRIC = "FindNeighbors particles/s (BuildTree + FindNeighbors per step)"
 
 
 def parse():
@@ -34,13 +42,22 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="P8M", choices=["U10k", "L1M", "P8M", "P16M"])
+    ap.add_argument("--workload", default="Batch64",
+                    choices=["Batch64", "U10k", "L1M", "P8M", "P16M"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
-    ap.add_argument("--bucket", type=int, default=0, help="bucket size s (0 = workload default)")
+    ap.add_argument("--bucket", type=int, default=0, help="single set: bucket size (0 = tuned)")
+    ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (default: package)")
+    ap.add_argument("--tune-out", default=None, help="write the cache here after tuning")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
-    ap.add_argument("--no-compare", action="store_true", help="skip the plain-FP64 comparison")
+    ap.add_argument("--no-compare", action="store_true", help="skip the comparison forms")
+    ap.add_argument("--no-single", action="store_true", help="Batch64: skip the P8M block")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
+
+
+def log(*a):
+    """Progress on stderr (the JSON line alone goes to stdout)."""
+    print("[bench %s]" % time.strftime("%H:%M:%S"), *a, file=sys.stderr, flush=True)
 
 
 def kernel_hash():
@@ -67,49 +84,235 @@ def load_traffic(kernel, workload):
     return None
 
 
-def run_steps(t, dx, dy, dz, dh, counts, offsets, nbrs, k):
+def phase_delta(s0, s1):
+    return {k: (s1["phase_ms"][k] - s0["phase_ms"][k]) /
+            max(1, s1["phase_calls"][k] - s0["phase_calls"][k]) for k in s1["phase_ms"]}
+
+
+def roofline(kernel_ms, tests, ops, kernel, workload):
+    achieved = tests * ops / (kernel_ms * 1e-3) / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
+            "frac": achieved / VALU_PEAK_TOPS, "kernel": kernel,
+            "traffic": load_traffic("sweep_kernel", workload),
+            "algorithmic_ops_per_launch": tests * ops}
+
+
+def search_hbm(n, total, search_ms):
+    # Compulsory HBM bytes of the whole search (both passes), per particle:
+    # coordinates 24 B + h 8 B + count 4 B + offset 8 B, plus 4 B per entry.
+    alg = n * (24 + 8 + 4 + 8) + 4 * total
+    gbs = alg / (search_ms * 1e-3) / 1e9
+    return {"algorithmic_bytes": alg, "search_ms": search_ms, "achieved_GBs": gbs,
+            "frac": gbs / HBM_PEAK_GBS}
+
+
+# ---------------------------------------------------------------------------
+# Single set: BuildTree (btree_rebuild) + pass 1 + pass 2 per step, eager.
+# ---------------------------------------------------------------------------
+def single_steps(t, dx, dy, dz, dh, counts, offsets, nbrs, k):
     for _ in range(k):
         t.rebuild(dx, dy, dz)
         t.count(dh, counts, offsets)
         t.fill(dh, counts, offsets, nbrs)
 
 
-def timed(t, dx, dy, dz, dh, counts, offsets, nbrs, steps, warmup):
+def single_timed(t, args, steps, warmup):
     import torch
-    run_steps(t, dx, dy, dz, dh, counts, offsets, nbrs, warmup)
+    single_steps(t, *args, warmup)
     torch.cuda.synchronize()
     s0 = t.stats()
     t0 = time.perf_counter()
-    run_steps(t, dx, dy, dz, dh, counts, offsets, nbrs, steps)
+    single_steps(t, *args, steps)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    el = time.perf_counter() - t0
     s1 = t.stats()
-    ph = {k: (s1["phase_ms"][k] - s0["phase_ms"][k]) /
-          max(1, s1["phase_calls"][k] - s0["phase_calls"][k]) for k in s1["phase_ms"]}
-    return t1 - t0, ph, s1
+    return el, phase_delta(s0, s1), s1
 
 
-def cpu_baseline(x, y, z, h, budget_s):
-    """The oracle (brute-force FP64 rows) on a bounded sample of the same
-    workload: rows drawn at random, particles/s = rows / wall time."""
+def bench_single(name, precision, steps, warmup, compare, tuner, bucket=0):
+    import torch
+    from paper_1910_02639_amd import btree, workloads as W
+    log("generate", name)
+    x, y, z, h, s = W.make(name)
+    n = len(x)
+    dx, dy, dz, dh = (torch.from_numpy(v).to("cuda:0") for v in (x, y, z, h))
+    if bucket:
+        prm = {"bucket_size": bucket}
+    else:
+        log("tune", name, precision)
+        prm = tuner.params_for(dx, dy, dz, dh, precision)
+    log("time", name, precision, prm)
+    counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+    t = btree.BTree(dx, dy, dz, precision=precision, timing=True, **prm)
+    _, _, total = t.count(dh, counts, offsets)
+    nbrs = torch.empty(total, dtype=torch.int32, device="cuda:0")
+    args = (dx, dy, dz, dh, counts, offsets, nbrs)
+    el, ph, st = single_timed(t, args, steps, warmup)
+    t.close()
+    ops = OPS_PER_TEST_F32 if precision == "fp32" else OPS_PER_TEST_F64
+    out = {"workload": name, "n": n, "params": prm, "value": n * steps / el,
+           "ms_per_step": 1e3 * el / steps, "phases_ms": ph,
+           "neighbours_total": total, "pair_tests_per_particle": st["pair_tests"] / n,
+           "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, st["pair_tests"]),
+           "exhaustive_items": st["brute_chunks"],
+           "tree": {"depth": st["depth"], "internal": st["n_internal"],
+                    "leaves": st["n_leaves"], "b_hist": st["b_hist"]},
+           "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], ops,
+                                "k_sweep<%s>" % precision, name),
+           "search_hbm": search_hbm(n, total, ph["pass1"] + ph["pass2"])}
+    if compare and precision == "fp32":
+        log("fp64 plain", name)
+        p64 = tuner.params_for(dx, dy, dz, dh, "fp64") if not bucket else prm
+        t2 = btree.BTree(dx, dy, dz, precision="fp64", timing=True, **p64)
+        k2 = max(2, min(steps, 5))
+        el2, ph2, _ = single_timed(t2, args, k2, 1)
+        t2.close()
+        out["fp64_plain"] = {"value": n * k2 / el2, "ms_per_step": 1e3 * el2 / k2,
+                             "params": p64, "search_ms": ph2["pass1"] + ph2["pass2"], "steps": k2}
+        out["fp32_filter_speedup"] = out["value"] / out["fp64_plain"]["value"]
+    return out, (x, y, z, h)
+
+
+# ---------------------------------------------------------------------------
+# Batch64: one captured graph per step vs one set per launch.
+# ---------------------------------------------------------------------------
+def per_set_loop(handles, views, bufs, k):
+    for _ in range(k):
+        for t, (x, y, z, h), (c, o, nb) in zip(handles, views, bufs):
+            t.rebuild(x, y, z)
+            t.count(h, c, o)
+            t.fill(h, c, o, nb)
+
+
+def bench_per_set(views, prms, precision, steps, warmup):
+    """Every set built and searched by its own calls, one after the other."""
+    import torch
+    from paper_1910_02639_amd import btree
+    handles, bufs = [], []
+    for (x, y, z, h), p in zip(views, prms):
+        t = btree.BTree(x, y, z, precision=precision, **p)
+        c = torch.empty(x.shape[0], dtype=torch.int32, device="cuda:0")
+        o = torch.empty(x.shape[0] + 1, dtype=torch.int64, device="cuda:0")
+        _, _, tot = t.count(h, c, o)
+        nb = torch.empty(max(tot, 1), dtype=torch.int32, device="cuda:0")
+        handles.append(t)
+        bufs.append((c, o, nb))
+    per_set_loop(handles, views, bufs, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    per_set_loop(handles, views, bufs, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for t in handles:
+        t.close()
+    n = sum(v[0].shape[0] for v in views)
+    return {"value": n * steps / el, "ms_per_step": 1e3 * el / steps, "steps": steps}
+
+
+def bench_batch(a, tuner):
+    import numpy as np
+    import torch
+    from paper_1910_02639_amd import btree, workloads as W
+    log("generate Batch64")
+    sets = W.batch(64, 0)
+    sizes = [len(s[0]) for s in sets]
+    n = int(sum(sizes))
+    host = [np.concatenate([s[c] for s in sets]) for c in range(4)]
+    dx, dy, dz, dh = (torch.from_numpy(v).to("cuda:0") for v in host)
+    offs = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    views = [tuple(t[int(offs[k]):int(offs[k + 1])] for t in (dx, dy, dz, dh))
+             for k in range(len(sizes))]
+    log("tune fp32 (%d sets, %d particles)" % (len(sizes), n))
+    prm32 = [tuner.params_for(*v, "fp32") for v in views]
+    log("batched graph runs")
+
+    B = btree.Batch(sizes, prm32, precision="fp32", timing=True)
+    counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+    c, o, nb, totals = B.find(dx, dy, dz, dh)
+    total = int(totals.sum())
+    del c, o, nb
+    nbrs = torch.empty(total, dtype=torch.int32, device="cuda:0")
+    for _ in range(a.warmup):
+        B.run(dx, dy, dz, dh, counts, offsets, nbrs)
+    torch.cuda.synchronize()
+    s0 = B.stats()
+    t0 = time.perf_counter()
+    for _ in range(a.steps):
+        B.run(dx, dy, dz, dh, counts, offsets, nbrs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = B.stats()
+    ph = phase_delta(s0, st)
+    B.close()
+
+    out = {
+        "metric": METRIC, "value": n * a.steps / el, "unit": "particles/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * el / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "Batch64", "sets": len(sizes), "n": n,
+                   "set_sizes_min_max": [int(min(sizes)), int(max(sizes))],
+                   "form": "captured HIP graph per step: 6 segments back to back, "
+                           "build + both search passes of all sets",
+                   "precision": "fp32_filter+fp64_band", "params": "autotuned per set",
+                   "buckets_used": sorted({p["bucket_size"] for p in prm32}),
+                   "neighbours_total": total, "neighbours_mean": total / n},
+        "phases_ms": ph,
+        "search_particles_per_s": n / ((ph["pass1"] + ph["pass2"]) * 1e-3),
+        "pair_tests_per_particle": st["pair_tests"] / n,
+        "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, st["pair_tests"]),
+        "exhaustive_items": st["brute_chunks"],
+        "graph": {"launches": st["graph_launches"], "recordings": st["graph_captures"]},
+        "tree": {"depth": st["depth"], "internal": st["n_internal"], "leaves": st["n_leaves"]},
+        "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], OPS_PER_TEST_F32,
+                             "k_sweep<fp32>", "Batch64"),
+        "search_hbm": search_hbm(n, total, ph["pass1"] + ph["pass2"]),
+    }
+    if not a.no_compare:
+        k2 = max(2, min(a.steps, 5))
+        log("tune fp64")
+        prm64 = [tuner.params_for(*v, "fp64") for v in views]
+        log("fp64 one set per launch")
+        f64 = bench_per_set(views, prm64, "fp64", k2, 1)
+        log("fp32 one set per launch")
+        f32 = bench_per_set(views, prm32, "fp32", k2, 1)
+        out["fp64_one_set_per_launch"] = f64
+        out["fp32_one_set_per_launch"] = f32
+        out["batched_fp32_vs_fp64_per_set"] = out["value"] / f64["value"]
+        out["batching_speedup_fp32"] = out["value"] / f32["value"]
+    return out, sets
+
+
+def cpu_baseline_sets(sets, budget_s):
+    """The oracle (brute-force FP64 rows) on a bounded sample: rows drawn at
+    random over the sets (weighted by size), each tested against every
+    particle of its set; particles/s = rows / wall time."""
     import numpy as np
     import oracle
     oracle.build(force=False)
     rng = np.random.default_rng(12345)
-    n = len(x)
-    probe = rng.integers(0, n, 32)
-    t0 = time.perf_counter()
-    oracle.counts(x, y, z, h, probe)
-    dt = time.perf_counter() - t0
-    m = int(max(32, min(n, 32 * budget_s / max(dt, 1e-6))))
-    rows = rng.integers(0, n, m)
-    t0 = time.perf_counter()
-    oracle.counts(x, y, z, h, rows)
-    dt = time.perf_counter() - t0
+    sizes = np.array([len(s[0]) for s in sets], dtype=np.float64)
+    w = sizes / sizes.sum()
+
+    def run(m):
+        pick = rng.choice(len(sets), m, p=w)
+        t0 = time.perf_counter()
+        for k in np.unique(pick):
+            x, y, z, h = sets[k]
+            rows = rng.integers(0, len(x), int((pick == k).sum()))
+            oracle.counts(x, y, z, h, rows)
+        return time.perf_counter() - t0
+
+    dt = run(64)
+    m = int(max(64, 64 * budget_s / max(dt, 1e-6)))
+    dt = run(m)
     cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     return {"value": m / dt, "unit": "particles/s", "cores": cores, "kind": "oracle",
-            "sample": "%d random rows of the %d-particle workload, each tested against all "
-                      "%d particles (%.1f s)" % (m, n, n, dt)}
+            "sample": "%d rows drawn over the %d sets (weighted by size), each tested against "
+                      "every particle of its set (%.1f s)" % (m, len(sets), dt)}
 
 
 def main():
@@ -118,78 +321,37 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
-    import numpy as np
-    import torch
-    from paper_1910_02639_amd import btree, workloads
-
-    x, y, z, h, s = workloads.make(a.workload)
-    if a.bucket:
-        s = a.bucket
-    n = len(x)
-    dev = "cuda:0"
-    dx, dy, dz, dh = (torch.from_numpy(v).to(dev) for v in (x, y, z, h))
-    counts = torch.empty(n, dtype=torch.int32, device=dev)
-    offsets = torch.empty(n + 1, dtype=torch.int64, device=dev)
-
-    t = btree.BTree(dx, dy, dz, bucket_size=s, precision=a.precision, timing=True)
-    _, _, total = t.count(dh, counts, offsets)
-    nbrs = torch.empty(total, dtype=torch.int32, device=dev)
-    elapsed, ph, st = timed(t, dx, dy, dz, dh, counts, offsets, nbrs, a.steps, a.warmup)
-    ms_per_step = 1e3 * elapsed / a.steps
-    value = n * a.steps / elapsed
-
-    # Dominant kernel of the search (the sweep: walk, stage, pair tests,
-    # rows) and its roofline.
-    kern = "sweep_kernel" if ph["sweep_kernel"] >= ph["place_kernel"] else "place_kernel"
-    kms = ph[kern]
-    tests = st["pair_tests"]
-    ops = OPS_PER_TEST_F32 if a.precision == "fp32" else OPS_PER_TEST_F64
-    achieved = tests * ops / (kms * 1e-3) / 1e12
-    roof = {"bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TOPS, "unit": "Tops/s",
-            "frac": achieved / VALU_PEAK_TOPS, "kernel": "k_sweep<%s>" % (
-                "fp32" if a.precision == "fp32" else "fp64"),
-            "traffic": load_traffic(kern, a.workload),
-            "algorithmic_ops_per_launch": tests * ops}
-    # Compulsory HBM bytes of the whole search (both passes), per particle:
-    # coordinates 24 B + h 8 B + count 4 B + offset 8 B, plus 4 B per entry.
-    alg_bytes = n * (24 + 8 + 4 + 8) + 4 * total
-    find_ms = ph["pass1"] + ph["pass2"]
-    hbm = {"algorithmic_bytes": alg_bytes, "search_ms": find_ms,
-           "achieved_GBs": alg_bytes / (find_ms * 1e-3) / 1e9,
-           "frac": alg_bytes / (find_ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
-
-    out = {
-        "metric": "FindNeighbors particles/s (BuildTree + FindNeighbors per step)",
-        "value": value, "unit": "particles/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if a.precision == "fp32" else "f64",
-        "data": "synthetic",
-        "config": {"workload": a.workload, "n": n, "bucket_size": s,
-                   "precision": "fp32_filter+fp64_band" if a.precision == "fp32" else "fp64",
-                   "neighbours_total": total, "neighbours_mean": total / n},
-        "phases_ms": ph,
-        "search_particles_per_s": n / (find_ms * 1e-3),
-        "pair_tests_per_s": tests / (ph["sweep_kernel"] * 1e-3),
-        "pair_tests_per_particle": tests / n,
-        "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, tests),
-        "exhaustive_items": st["brute_chunks"],
-        "tree": {"depth": st["depth"], "internal": st["n_internal"], "leaves": st["n_leaves"],
-                 "b_hist": st["b_hist"]},
-        "roofline": roof,
-        "search_hbm": hbm,
-    }
-    t.close()
-    if not a.no_compare and a.precision == "fp32":
-        t2 = btree.BTree(dx, dy, dz, bucket_size=s, precision="fp64", timing=True)
-        k2 = max(2, min(a.steps, 5))
-        el2, ph2, _ = timed(t2, dx, dy, dz, dh, counts, offsets, nbrs, k2, 1)
-        out["fp64_plain"] = {"value": n * k2 / el2, "ms_per_step": 1e3 * el2 / k2,
-                             "search_ms": ph2["pass1"] + ph2["pass2"], "steps": k2}
-        out["fp32_filter_speedup"] = out["value"] / out["fp64_plain"]["value"]
-        t2.close()
+    from paper_1910_02639_amd import autotune
+    tuner = autotune.Tuner(a.tune_cache or autotune.CACHE)
+    if a.workload == "Batch64":
+        out, sets = bench_batch(a, tuner)
+        if not a.no_single:
+            p8, _ = bench_single("P8M", "fp32", max(2, min(a.steps, 10)), 2, not a.no_compare,
+                                 tuner)
+            out["single_set_P8M"] = p8
+    else:
+        r, xyzh = bench_single(a.workload, a.precision, a.steps, a.warmup, not a.no_compare,
+                               tuner, a.bucket)
+        out = {"metric": METRIC, "value": r["value"], "unit": "particles/s", "n_gpus": 1,
+               "steps": a.steps, "warmup": a.warmup, "ms_per_step": r["ms_per_step"],
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+               "dtype": "f32+f64" if a.precision == "fp32" else "f64", "data": "synthetic",
+               "config": {"workload": a.workload, "n": r["n"], "params": r["params"],
+                          "precision": "fp32_filter+fp64_band" if a.precision == "fp32"
+                          else "fp64", "neighbours_total": r["neighbours_total"]}}
+        for k in ("phases_ms", "pair_tests_per_particle", "fp64_confirmed_fraction",
+                  "exhaustive_items", "tree", "roofline", "search_hbm", "fp64_plain",
+                  "fp32_filter_speedup"):
+            if k in r:
+                out[k] = r[k]
+        sets = [xyzh]
+    if tuner.tuned_now:
+        out["tuned_now"] = tuner.tuned_now
+        if a.tune_out:
+            tuner.save(a.tune_out)
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(x, y, z, h, a.cpu_seconds)
+        log("cpu baseline (oracle)")
+        out["cpu_baseline"] = cpu_baseline_sets(sets, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

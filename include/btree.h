@@ -86,7 +86,7 @@ typedef struct {
     int64_t total;          /* neighbour entries                              */
     int64_t pair_tests;     /* candidate pairs tested (FP32 or FP64)          */
     int64_t fp64_confirms;  /* FP32-filter pairs re-tested in FP64            */
-    int64_t brute_chunks;   /* work items that took the exhaustive path       */
+    int64_t brute_chunks;   /* queries that took the exhaustive path          */
     int64_t candidates;     /* culled candidates staged, summed over items    */
     /* with params.timing = 1, device time of each phase summed over the
        calls since btree_build (btree_rebuild keeps counting):
@@ -95,6 +95,9 @@ typedef struct {
        [3] whole pass 1, [4] whole pass 2; phase_calls counts the calls.   */
     double  phase_ms[5];
     int64_t phase_calls[5];
+    int64_t split_items;    /* work items whose candidates overflowed shared
+                               memory and were searched again in groups of 8
+                               queries, then singly                            */
 } btree_stats_t;
 
 typedef struct btree_tree* btree_handle;
@@ -174,7 +177,7 @@ btree_status btree_destroy(btree_handle t);
 /* ------------------------------------------------------------------------
  * Batched form: many independent particle sets, each with its own b-tree
  * (Algorithm 1) and its own neighbour lists (Algorithm 2), built and
- * searched together by one captured HIP graph per call.
+ * searched together by a captured HIP graph per call.
  * ---------------------------------------------------------------------- */
 typedef struct btree_batch* btree_batch_handle;
 
@@ -183,7 +186,7 @@ typedef struct btree_batch* btree_batch_handle;
  * k is particles [set_offsets[k], set_offsets[k+1]) of the concatenated
  * arrays (empty sets allowed).  per_set: HOST btree_params[nsets] (NULL =
  * defaults for every set); s, alpha, beta and max_depth may differ between
- * sets, precision must not, timing must be 0.  Allocates the device pools
+ * sets, precision and timing must not.  Allocates the device pools
  * of the batch; queues nothing.  Errors: EINVAL, ENOMEM, EDEVICE. */
 btree_status btree_batch_create(int32_t nsets, const int64_t* set_offsets,
                                 const btree_params* per_set,
@@ -200,12 +203,15 @@ btree_status btree_batch_create(int32_t nsets, const int64_t* set_offsets,
  * nbrs: device int32[capacity] (may be NULL when capacity = 0).
  * totals: HOST int64[nsets] or NULL, entries per set; total: HOST int64,
  *   their sum.
- * The work is one graph launch on hip_stream, recorded on the first call
- * with a given set of pointers and capacity and replayed on later calls
- * with the same ones.  The first call on a handle first runs an eager build
- * and count pass to size the pools.  The call waits for the stream.  When
- * a pool proves too small for new data, the handle grows it, records the
- * graph again and repeats the run.
+ * The work is a captured HIP graph, recorded on the first call with a given
+ * set of pointers and capacity and replayed on later calls with the same
+ * ones: six graph segments (build; search set-up; sweep; counts and
+ * offsets; row placement; exhaustive rows and totals) launched back to back
+ * on hip_stream with no host work between them (so that HIP events between
+ * segments can time the steps).  The first call on a handle first runs an
+ * eager build and count pass to size the pools.  The call waits for the
+ * stream.  When a pool proves too small for new data, the handle grows it,
+ * records the graph again and repeats the run.
  * Errors: EINVAL (NULL arrays with n_total > 0, capacity < 0, non-finite
  * coordinate, h < 0 or non-finite: then no caller output is written),
  * EOVERFLOW (capacity < total: counts, offsets, totals and *total are
@@ -218,14 +224,49 @@ btree_status btree_batch_run(btree_batch_handle b, const double* x,
                              int64_t* total, void* hip_stream);
 
 /* Shape of the batch's forest and counters of its last run, summed over
- * the sets (depth and max_leaf: maxima).  phase_ms is zero; phase_calls[0]
- * counts graph launches and phase_calls[1] graph recordings.
+ * the sets (depth and max_leaf: maxima).  With timing = 1, phase_ms holds
+ * device time of the graph runs (HIP events between segments; the first
+ * call's sizing run is not counted), with the phases of btree_stats_t.
  * Errors: EINVAL (NULL argument). */
 btree_status btree_batch_stats(btree_batch_handle b, btree_stats_t* out);
+
+/* Graph launches made and graph recordings taken by the handle so far.
+ * Errors: EINVAL (NULL argument). */
+btree_status btree_batch_graph_counts(btree_batch_handle b, int64_t* launches,
+                                      int64_t* recordings);
 
 /* Releases the batch and its device memory (NULL is a no-op); waits for
  * the device first. */
 btree_status btree_batch_destroy(btree_batch_handle b);
+
+/* ------------------------------------------------------------------------
+ * Autotuning of s and beta (the parameters of Table 1 and Eq. 4).  Results
+ * do not depend on the parameters, so a tuner can only change speed.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t n_bucket;       /* candidate bucket sizes s, 1..16              */
+    int32_t bucket[16];
+    int32_t n_beta;         /* candidate beta values, 1..8                  */
+    double  beta[8];
+    int32_t repeats;        /* timed runs per candidate (median), 1..100   */
+    int32_t reserved[3];    /* must be zero                                 */
+} btree_tune_space;
+
+/* Default space: s in {16, 24, 32, 48, 64, 96, 128, 192, 256}, beta in
+ * {0.3, 0.5, 0.8}, 3 repeats.  Errors: EINVAL (NULL). */
+btree_status btree_tune_space_default(btree_tune_space* space);
+
+/* Times BuildTree + both FindNeighbors passes on the given particles for
+ * every (s, beta) of `space` (NULL = default), other parameters from `base`
+ * (NULL = defaults), with HIP events on hip_stream, and returns in *best
+ * the parameters of the fastest median and in *best_ms that median.
+ * all_ms: HOST double[n_bucket * n_beta] (row-major by bucket) or NULL.
+ * Allocates its own device buffers; synchronises the stream.
+ * Errors: EINVAL (bad arguments or data), ENOMEM, EDEVICE. */
+btree_status btree_tune(const double* x, const double* y, const double* z,
+                        const double* h, int64_t n, const btree_params* base,
+                        const btree_tune_space* space, btree_params* best,
+                        double* best_ms, double* all_ms, void* hip_stream);
 
 /* Message of the last failed call on this host thread ("" if none). */
 const char* btree_last_error(void);

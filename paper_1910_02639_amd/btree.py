@@ -29,7 +29,8 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFL
 
 SYMBOLS = ["btree_params_default", "btree_build", "btree_rebuild", "btree_find_neighbors",
            "btree_stats", "btree_export", "btree_destroy", "btree_last_error",
-           "btree_batch_create", "btree_batch_run", "btree_batch_stats", "btree_batch_destroy"]
+           "btree_batch_create", "btree_batch_run", "btree_batch_stats", "btree_batch_destroy",
+           "btree_batch_graph_counts", "btree_tune_space_default", "btree_tune"]
 
 
 class Params(ctypes.Structure):
@@ -47,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("b_hist", ctypes.c_int64 * 65), ("total", ctypes.c_int64),
                 ("pair_tests", ctypes.c_int64), ("fp64_confirms", ctypes.c_int64),
                 ("brute_chunks", ctypes.c_int64), ("candidates", ctypes.c_int64),
-                ("phase_ms", ctypes.c_double * 5), ("phase_calls", ctypes.c_int64 * 5)]
+                ("phase_ms", ctypes.c_double * 5), ("phase_calls", ctypes.c_int64 * 5),
+                ("split_items", ctypes.c_int64)]
 
 PHASES = ["build", "sweep_kernel", "place_kernel", "pass1", "pass2"]
 
@@ -95,6 +97,8 @@ def lib():
         L.btree_batch_stats.argtypes = [P, ctypes.POINTER(Stats)]
         L.btree_batch_destroy.restype = ctypes.c_int
         L.btree_batch_destroy.argtypes = [P]
+        L.btree_batch_graph_counts.restype = ctypes.c_int
+        L.btree_batch_graph_counts.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
         _lib = L
     return _lib
 
@@ -280,7 +284,7 @@ class Batch:
             raise ValueError("params_per_set needs one entry per set")
         arr = (Params * self.nsets)()
         for k, d in enumerate(params_per_set):
-            d = dict(d)
+            d = dict(kw, **d)  # keyword arguments apply to every set unless overridden
             d.setdefault("precision", precision)
             arr[k] = params(**d)
         self._params = arr
@@ -351,8 +355,12 @@ class Batch:
         s = Stats()
         _check(lib().btree_batch_stats(self._h, ctypes.byref(s)))
         d = _stats_dict(s)
-        d["graph_launches"] = int(s.phase_calls[0])
-        d["graph_captures"] = int(s.phase_calls[1])
+        d["phase_ms"] = {k: float(s.phase_ms[i]) for i, k in enumerate(PHASES)}
+        d["phase_calls"] = {k: int(s.phase_calls[i]) for i, k in enumerate(PHASES)}
+        la, rec = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().btree_batch_graph_counts(self._h, ctypes.byref(la), ctypes.byref(rec)))
+        d["graph_launches"] = int(la.value)
+        d["graph_captures"] = int(rec.value)
         return d
 
 

@@ -1,8 +1,10 @@
-// Batched form: many independent particle sets built and searched by one
+// Batched form: many independent particle sets built and searched by a
 // captured HIP graph.  The sets share one control block, one set of pools
 // and one launch sequence (set id in the top bits of the Morton key, per-set
 // roots, work items tagged with their set), so the whole batch costs the
-// launches of a single tree.
+// launches of a single tree.  The sequence is recorded as a few graph
+// segments (build, search steps) launched back to back with no host work
+// between them, so HIP events on the caller's stream can time the steps.
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -11,23 +13,29 @@
 
 namespace bt {
 
+enum { kSegBuild = 0, kSegBegin, kSegSweep, kSegCounts, kSegPlace, kSegFill, kSegs };
+
 struct Batch {
     Tree t;
     hipStream_t cs = nullptr;       // private stream the graph is captured on
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[kSegs] = {};
+    hipGraphExec_t exec[kSegs] = {};
     const void* key[7] = {};        // caller pointers baked into the graph
     int64_t key_cap = -1;
     bool primed = false;            // an eager run has sized the pools
+    bool recorded = false;
     int64_t launches = 0;
     int64_t captures = 0;
     std::vector<int64_t> host_tot;  // per-set totals of the last run
 
     void drop_graph() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        exec = nullptr;
-        graph = nullptr;
+        for (int k = 0; k < kSegs; ++k) {
+            if (exec[k]) (void)hipGraphExecDestroy(exec[k]);
+            if (graph[k]) (void)hipGraphDestroy(graph[k]);
+            exec[k] = nullptr;
+            graph[k] = nullptr;
+        }
+        recorded = false;
     }
     ~Batch() {
         drop_graph();
@@ -46,7 +54,8 @@ void check_set_params(const btree_params& p, const btree_params& p0) {
         fail(BTREE_EINVAL, "precision must be BTREE_FP64 or BTREE_FP32_FILTER");
     if (p.precision != p0.precision) fail(BTREE_EINVAL, "all sets of a batch need one precision");
     if (p.group_size != 0 && p.group_size != kGroup) fail(BTREE_EINVAL, "group_size must be 0 or 64");
-    if (p.timing != 0) fail(BTREE_EINVAL, "timing is not available in a batch (use 0)");
+    if (p.timing != 0 && p.timing != 1) fail(BTREE_EINVAL, "timing must be 0 or 1");
+    if (p.timing != p0.timing) fail(BTREE_EINVAL, "all sets of a batch need one timing flag");
     for (int k = 0; k < 5; ++k)
         if (p.reserved[k] != 0) fail(BTREE_EINVAL, "reserved fields must be zero");
 }
@@ -55,33 +64,68 @@ __global__ void k_zero_offsets(int64_t* __restrict__ offsets) {
     if (threadIdx.x == 0 && blockIdx.x == 0) offsets[0] = 0;
 }
 
-// Records build + search of every set into a graph on the private stream.
-void capture(Batch& B, const double* x, const double* y, const double* z, const double* h,
-             int32_t* counts, int64_t* offsets, int32_t* nbrs, int64_t capacity) {
-    Tree& t = B.t;
-    B.drop_graph();
+// Records one segment: whatever `queue` puts on the private stream.
+template <class F>
+void record(Batch& B, int seg, F&& queue) {
     BT_HIP(hipStreamBeginCapture(B.cs, hipStreamCaptureModeThreadLocal));
     try {
-        build_queue(t, x, y, z, (int)t.level_cap, false, B.cs);
-        find_queue(t, h, counts, offsets, nbrs, capacity, t.tot.as<int64_t>(), B.cs);
+        queue(B.cs);
     } catch (...) {
         hipGraph_t g = nullptr;
         (void)hipStreamEndCapture(B.cs, &g);
         if (g) (void)hipGraphDestroy(g);
         throw;
     }
-    BT_HIP(hipStreamEndCapture(B.cs, &B.graph));
-    BT_HIP(hipGraphInstantiate(&B.exec, B.graph, nullptr, nullptr, 0));
+    BT_HIP(hipStreamEndCapture(B.cs, &B.graph[seg]));
+    BT_HIP(hipGraphInstantiate(&B.exec[seg], B.graph[seg], nullptr, nullptr, 0));
+}
+
+// Records build + search of every set.
+void capture(Batch& B, const double* x, const double* y, const double* z, const double* h,
+             int32_t* counts, int64_t* offsets, int32_t* nbrs, int64_t capacity) {
+    Tree& t = B.t;
+    B.drop_graph();
+    record(B, kSegBuild, [&](hipStream_t s) { build_queue(t, x, y, z, (int)t.level_cap, false, s); });
+    record(B, kSegBegin, [&](hipStream_t s) { find_begin(t, h, s); });
+    record(B, kSegSweep, [&](hipStream_t s) { find_sweep(t, h, counts, t.chunk_cap, s); });
+    record(B, kSegCounts, [&](hipStream_t s) { find_counts_end(t, h, counts, offsets, s); });
+    record(B, kSegPlace, [&](hipStream_t s) { find_place(t, counts, offsets, nbrs, capacity, s); });
+    record(B, kSegFill, [&](hipStream_t s) {
+        find_fill_end(t, h, offsets, nbrs, capacity, t.tot.as<int64_t>(), s);
+    });
+    B.recorded = true;
     const void* k[7] = {x, y, z, h, counts, offsets, nbrs};
     std::memcpy(B.key, k, sizeof k);
     B.key_cap = capacity;
     ++B.captures;
 }
 
+// Launches the segments back to back on the caller's stream.
+void launch(Batch& B, hipStream_t st) {
+    Timer& T = B.t.timer;
+    T.start(kPhBuild, st);
+    BT_HIP(hipGraphLaunch(B.exec[kSegBuild], st));
+    T.stop(kPhBuild, st);
+    T.start(kPhPass1, st);
+    BT_HIP(hipGraphLaunch(B.exec[kSegBegin], st));
+    T.start(kPhSweep, st);
+    BT_HIP(hipGraphLaunch(B.exec[kSegSweep], st));
+    T.stop(kPhSweep, st);
+    BT_HIP(hipGraphLaunch(B.exec[kSegCounts], st));
+    T.stop(kPhPass1, st);
+    T.start(kPhPass2, st);
+    T.start(kPhPlace, st);
+    BT_HIP(hipGraphLaunch(B.exec[kSegPlace], st));
+    T.stop(kPhPlace, st);
+    BT_HIP(hipGraphLaunch(B.exec[kSegFill], st));
+    T.stop(kPhPass2, st);
+    ++B.launches;
+}
+
 bool same_key(const Batch& B, const double* x, const double* y, const double* z, const double* h,
               const int32_t* counts, const int64_t* offsets, const int32_t* nbrs, int64_t cap) {
     const void* k[7] = {x, y, z, h, counts, offsets, nbrs};
-    return B.exec && std::memcmp(B.key, k, sizeof k) == 0 && B.key_cap == cap;
+    return B.recorded && std::memcmp(B.key, k, sizeof k) == 0 && B.key_cap == cap;
 }
 
 // First run: an eager build and count pass size the level count, the work
@@ -89,10 +133,13 @@ bool same_key(const Batch& B, const double* x, const double* y, const double* z,
 void prime(Batch& B, const double* x, const double* y, const double* z, const double* h,
            int32_t* counts, int64_t* offsets, hipStream_t st) {
     Tree& t = B.t;
+    const bool timing = t.timer.on;
+    t.timer.on = false;  // phase times count graph runs only
     build_tree(t, x, y, z, st);
     t.level_cap = std::max<int64_t>(1, std::min<int64_t>(t.levels_seen + 1, 66));
     t.chunk_cap = t.n_chunks + t.n_chunks / 4 + 64;
     (void)find_pass1(t, h, counts, offsets, st);
+    t.timer.on = timing;
     B.primed = true;
 }
 
@@ -153,7 +200,7 @@ btree_status btree_batch_create(int32_t nsets, const int64_t* set_offsets,
         Tree& t = B.t;
         try {
             t.prm = prm[0];
-            t.timer.on = false;
+            t.timer.on = prm[0].timing != 0;
             if (hipGetDevice(&t.device) != hipSuccess) t.device = 0;
             BT_HIP(hipStreamCreateWithFlags(&B.cs, hipStreamNonBlocking));
             plan_sets(t, nsets, set_offsets, prm.data());
@@ -198,8 +245,7 @@ btree_status btree_batch_run(btree_batch_handle H, const double* x, const double
         for (int attempt = 0;; ++attempt) {
             if (!same_key(B, x, y, z, h, counts, offsets, nbrs, capacity))
                 capture(B, x, y, z, h, counts, offsets, nbrs, capacity);
-            BT_HIP(hipGraphLaunch(B.exec, st));
-            ++B.launches;
+            launch(B, st);
             BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
             BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
             BT_HIP(hipMemcpyAsync(B.host_tot.data(), t.tot.p, sizeof(int64_t) * t.nsets,
@@ -251,8 +297,9 @@ btree_status btree_batch_stats(btree_batch_handle H, btree_stats_t* out) {
         set_error("btree_batch_stats: NULL argument");
         return BTREE_EINVAL;
     }
-    const Batch& B = H->b;
-    const Tree& t = B.t;
+    Batch& B = H->b;
+    Tree& t = B.t;
+    t.timer.fold_all();
     std::memset(out, 0, sizeof *out);
     out->n = t.n;
     out->n_internal = t.n_internal;
@@ -268,8 +315,23 @@ btree_status btree_batch_stats(btree_batch_handle H, btree_stats_t* out) {
     out->fp64_confirms = (int64_t)t.host_stats.confirms;
     out->brute_chunks = (int64_t)t.host_stats.brute;
     out->candidates = (int64_t)t.host_stats.candidates;
-    out->phase_calls[0] = B.launches;
-    out->phase_calls[1] = B.captures;
+    out->split_items = (int64_t)t.host_stats.split;
+    for (int k = 0; k < kPhases; ++k) {
+        out->phase_ms[k] = t.timer.sum_ms[k];
+        out->phase_calls[k] = t.timer.calls[k];
+    }
+    set_error("");
+    return BTREE_OK;
+}
+
+btree_status btree_batch_graph_counts(btree_batch_handle H, int64_t* launches,
+                                      int64_t* recordings) {
+    if (!H || !launches || !recordings) {
+        set_error("btree_batch_graph_counts: NULL argument");
+        return BTREE_EINVAL;
+    }
+    *launches = H->b.launches;
+    *recordings = H->b.captures;
     set_error("");
     return BTREE_OK;
 }

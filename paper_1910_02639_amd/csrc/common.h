@@ -135,6 +135,7 @@ struct Stats {  // device-side counters
     unsigned long long confirms;
     unsigned long long brute;
     unsigned long long candidates;
+    unsigned long long split;
     unsigned long long b_hist[65];
 };
 
@@ -171,7 +172,7 @@ constexpr int kOvfTree = kOvfNodes | kOvfLeaves | kOvfCtab | kOvfHist | kOvfLeve
 struct Ctl {
     int32_t cur_nb, cur_ne;     // cells of the level being split
     int32_t lvm;                // cur_ne - cur_nb (a device length for scans)
-    int32_t pad0;
+    uint32_t nsplit;            // work items split for overflowing (atomic)
     int32_t next_nb, next_ne;   // cells of the next level
     int32_t n_nodes, n_leaves;  // allocated so far
     int64_t ct_len;             // child-table entries allocated
@@ -266,7 +267,8 @@ struct Tree {
     DBuf lrange;   // int2 per leaf: smallest and largest original index
     DBuf chunks;   // Chunk[n_chunks]
     DBuf stats;    // Stats
-    DBuf blist;    // int32 work-item ids taken by the exhaustive path
+    DBuf split;    // Chunk per work item whose candidates overflowed (split further)
+    DBuf blist;    // Chunk per query taken by the exhaustive path
     DBuf scan_tmp; // scan block sums
     DBuf scratch;  // int32 rows of the search, in work-item order
     DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)
@@ -400,11 +402,18 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
 // Eager build: queue, wait, grow pools and redo on overflow.
 void build_tree(Tree& t, const double* x, const double* y, const double* z,
                 hipStream_t st);
-// Search queued without host reads (for graphs): pass 1, then pass 2 into
-// nbrs of `capacity` entries (nothing written if the lists do not fit), then
-// per-set totals when `totals` is non-null.
-void find_queue(Tree& t, const double* h, int32_t* counts, int64_t* offsets, int32_t* nbrs,
-                int64_t capacity, int64_t* totals, hipStream_t st);
+// Steps of the search, each queued without host reads (a captured graph
+// may hold them): reset and h check; the sweep over `grid` work items;
+// exhaustive counts and the offsets scan; placement of the rows into nbrs
+// of `capacity` entries (nothing written if they do not fit); exhaustive
+// rows and per-set totals (when `totals` is non-null).
+void find_begin(Tree& t, const double* h, hipStream_t st);
+void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStream_t st);
+void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st);
+void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
+                int64_t capacity, hipStream_t st);
+void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,
+                   int64_t capacity, int64_t* totals, hipStream_t st);
 // Sizes the search scratch for at least `entries` list entries.
 void find_reserve(Tree& t, int64_t entries);
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets,

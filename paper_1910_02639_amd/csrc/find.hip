@@ -167,9 +167,10 @@ template <> struct Ent<false> {
 
 // One work item of the sweep: walk, stage, order by original index, test,
 // rows out.  Called by every thread of the workgroup with the same item.
+// Returns false, having written nothing, when the item's candidates do not
+// fit the shared-memory budget (the caller then splits it).
 template <bool F32>
-__device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict__ chunks,
-                                           const double4* __restrict__ pos,
+__device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __restrict__ pos,
                                            const double4* __restrict__ orig,
                                            const Node* __restrict__ nodes,
                                            const int32_t* __restrict__ ctab,
@@ -180,8 +181,7 @@ __device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict
                                            int32_t* __restrict__ counts,
                                            int64_t* __restrict__ soff,
                                            int32_t* __restrict__ scratch, int64_t scap,
-                                           Ctl* __restrict__ ctl, int32_t* __restrict__ blist,
-                                           Stats* __restrict__ stats) {
+                                           Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
     using E = typename Ent<F32>::T;
     __shared__ E s_cand[kCMax];
     __shared__ int32_t s_cnt[kWaves][64];
@@ -195,7 +195,6 @@ __device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict
     __shared__ int s_nleaf, s_ovf, s_kmin, s_kmax, s_C, s_big, s_total;
     __shared__ unsigned long long s_base;
 
-    const Chunk ch = chunks[ci];
     // The item's set: its root, and the base that makes indices set-local.
     const int32_t root_code = __builtin_amdgcn_readfirstlane(sets[ch.set].root);
     const int sbeg = __builtin_amdgcn_readfirstlane((int)sets[ch.set].beg);
@@ -350,14 +349,7 @@ __device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict
         }
     }
     __syncthreads();
-    if (s_ovf) {
-        if (t == 0) {
-            blist[atomicAdd(&ctl->nbrute, 1u)] = ci;
-            atomicAdd(&stats->brute, 1ull);
-        }
-        if (w == 0 && qv) soff[qidx] = -1;
-        return;
-    }
+    if (s_ovf) return false;
     const int nleaf = __builtin_amdgcn_readfirstlane(s_nleaf);
     const int kmin = __builtin_amdgcn_readfirstlane(s_kmin);
     const int kmax = __builtin_amdgcn_readfirstlane(s_kmax);
@@ -384,14 +376,7 @@ __device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict
     if (lane == 0) atomicAdd(&s_C, myC);
     __syncthreads();
     const int C = __builtin_amdgcn_readfirstlane(s_C);
-    if (C > kCMax) {
-        if (t == 0) {
-            blist[atomicAdd(&ctl->nbrute, 1u)] = ci;
-            atomicAdd(&stats->brute, 1ull);
-        }
-        if (w == 0 && qv) soff[qidx] = -1;
-        return;
-    }
+    if (C > kCMax) return false;
     int bstart, bcount;
     {
         int64_t tot;
@@ -406,14 +391,7 @@ __device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict
     if (s_big) {
         int P2 = 1;
         while (P2 < C) P2 <<= 1;
-        if (P2 > kCMax) {
-            if (t == 0) {
-                blist[atomicAdd(&ctl->nbrute, 1u)] = ci;
-                atomicAdd(&stats->brute, 1ull);
-            }
-            if (w == 0 && qv) soff[qidx] = -1;
-            return;
-        }
+        if (P2 > kCMax) return false;
     }
 
     // Stage, pass 2: place each candidate in its bucket.
@@ -595,7 +573,7 @@ __device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict
         // once the scratch has grown to the need the cursor now holds.
         if (t == 0) atomicOr(&ctl->overflow, kOvfScratch);
         if (w == 0 && qv) soff[qidx] = -2;
-        return;
+        return true;
     }
     if (w == 0 && qv) soff[qidx] = base + s_qoff[lane];
     // Rows: lane q of wavefront w writes the hits of its block right after
@@ -617,11 +595,14 @@ __device__ __forceinline__ void sweep_item(const int ci, const Chunk* __restrict
             }
         }
     }
+    return true;
 }
 
 // The sweep: workgroup g takes work item g.  The grid is the host's bound on
 // the item count (exact after an eager build; a captured graph uses a bound
-// with a margin and reports an item count above it as an overflow).
+// with a margin and reports an item count above it as an overflow).  Items
+// whose candidates overflow the shared-memory budget are listed for
+// k_sweep_split.
 template <bool F32>
 __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                const double4* __restrict__ pos,
@@ -635,7 +616,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                int32_t* __restrict__ counts,
                                                int64_t* __restrict__ soff,
                                                int32_t* __restrict__ scratch, int64_t scap,
-                                               Ctl* __restrict__ ctl, int32_t* __restrict__ blist,
+                                               Ctl* __restrict__ ctl, Chunk* __restrict__ split,
                                                Stats* __restrict__ stats) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     const int nch = ctl->n_chunks;
@@ -643,8 +624,62 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     if (ci == 0 && threadIdx.x == 0 && (unsigned)nch > gridDim.x)
         atomicOr(&ctl->overflow, kOvfChunks);
     if (ci >= nch) return;
-    sweep_item<F32>(ci, chunks, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
-                    scratch, scap, ctl, blist, stats);
+    const Chunk ch = chunks[ci];
+    if (!sweep_item<F32>(ch, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff, scratch,
+                         scap, ctl, stats)) {
+        if (threadIdx.x == 0) {
+            split[atomicAdd(&ctl->nsplit, 1u)] = ch;
+            atomicAdd(&stats->split, 1ull);
+        }
+    }
+}
+
+constexpr int kSubGroup = 8;  // queries per sub-item of a split work item
+
+// Work items that overflowed, cut into sub-items of kSubGroup queries (each
+// with its own, smaller box E), then into single queries; a single query
+// that still overflows takes the exhaustive path.  Persistent over the list.
+template <bool F32>
+__global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ split,
+                                                     const double4* __restrict__ pos,
+                                                     const double4* __restrict__ orig,
+                                                     const Node* __restrict__ nodes,
+                                                     const int32_t* __restrict__ ctab,
+                                                     const Leaf* __restrict__ leaves,
+                                                     const int2* __restrict__ lrange,
+                                                     const SetDev* __restrict__ sets,
+                                                     const double* __restrict__ h,
+                                                     int32_t* __restrict__ counts,
+                                                     int64_t* __restrict__ soff,
+                                                     int32_t* __restrict__ scratch, int64_t scap,
+                                                     Ctl* __restrict__ ctl,
+                                                     Chunk* __restrict__ brute,
+                                                     Stats* __restrict__ stats) {
+    if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
+    const uint32_t ns = ctl->nsplit;
+    for (uint32_t k = blockIdx.x; k < ns; k += gridDim.x) {
+        const Chunk ch = split[k];
+        for (int q0 = 0; q0 < ch.cnt; q0 += kSubGroup) {
+            const Chunk sub{ch.beg + q0, min(kSubGroup, ch.cnt - q0), ch.set, 0};
+            __syncthreads();
+            if (sweep_item<F32>(sub, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
+                                scratch, scap, ctl, stats))
+                continue;
+            for (int q = 0; q < sub.cnt; ++q) {
+                const Chunk one{sub.beg + q, 1, ch.set, 0};
+                __syncthreads();
+                if (sweep_item<F32>(one, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts,
+                                    soff, scratch, scap, ctl, stats))
+                    continue;
+                if (threadIdx.x == 0) {
+                    brute[atomicAdd(&ctl->nbrute, 1u)] = one;
+                    soff[(int)pos[one.beg].w] = -1;
+                    atomicAdd(&stats->brute, 1ull);
+                }
+            }
+        }
+        __syncthreads();
+    }
 }
 
 // Rows from the scratch into the CSR array (original order, coalesced).  A
@@ -686,11 +721,10 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
     }
 }
 
-// Exhaustive path for the listed items: every particle of the item's set in
-// original index order.  Persistent over the list.
+// Exhaustive path for the listed queries: every particle of the query's set
+// in original index order.  Persistent over the list.
 template <int MODE>
-__global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ chunks,
-                                               const int32_t* __restrict__ blist,
+__global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ blist,
                                                const SetDev* __restrict__ sets,
                                                const double4* __restrict__ pos,
                                                const double4* __restrict__ orig,
@@ -705,7 +739,7 @@ __global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ chunks,
     const uint32_t nb = ctl->nbrute;
     const int t = threadIdx.x, lane = t & 63, w = t >> 6;
     for (uint32_t k = blockIdx.x; k < nb; k += gridDim.x) {
-        const Chunk ch = chunks[blist[k]];
+        const Chunk ch = blist[k];
         const int64_t jb = sets[ch.set].beg, jn = sets[ch.set].n;
         for (int q = 0; q < ch.cnt; ++q) {
             const double4 qp = pos[ch.beg + q];
@@ -750,6 +784,7 @@ __global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ chunks,
 __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
     if (threadIdx.x == 0) {
         ctl->queue = 0;
+        ctl->nsplit = 0;
         ctl->nbrute = 0;
         ctl->cursor = 0;
         ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
@@ -758,6 +793,7 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
         stats->confirms = 0;
         stats->brute = 0;
         stats->candidates = 0;
+        stats->split = 0;
     }
 }
 
@@ -779,54 +815,27 @@ __global__ void k_set_totals(const int64_t* __restrict__ offsets, const SetDev* 
 }
 
 constexpr unsigned kBruteGrid = 512;
+constexpr unsigned kSplitGrid = 1024;
 
 template <bool F32>
 void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipStream_t st) {
-    t.timer.start(kPhSweep, st);
     hipLaunchKernelGGL((k_sweep<F32>), dim3(grid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
-                       t.scratch.as<int32_t>(), t.scap, t.ctl.as<Ctl>(), t.blist.as<int32_t>(),
+                       t.scratch.as<int32_t>(), t.scap, t.ctl.as<Ctl>(), t.split.as<Chunk>(),
                        t.stats.as<Stats>());
     BT_LAUNCH();
-    t.timer.stop(kPhSweep, st);
-    hipLaunchKernelGGL((k_brute<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
-                       t.blist.as<int32_t>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), h, counts, nullptr, t.n, (int64_t)0, nullptr,
-                       t.ctl.as<Ctl>());
-    BT_LAUNCH();
 }
 
-// Pass 1 queued: counts, rows into the scratch, offsets.
-void queue_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, unsigned grid,
-                 hipStream_t st) {
-    const bool f32 = t.prm.precision == BTREE_FP32_FILTER;
-    hipLaunchKernelGGL(k_find_reset, dim3(1), dim3(64), 0, st, t.ctl.as<Ctl>(), t.stats.as<Stats>());
-    BT_LAUNCH();
-    hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
-                       st, h, t.n, t.ctl.as<Ctl>());
-    BT_LAUNCH();
-    if (f32) launch_sweep<true>(t, h, counts, grid, st);
-    else launch_sweep<false>(t, h, counts, grid, st);
-    scan_exclusive_i32(counts, offsets, t.n, t, st, &t.ctl.as<Ctl>()->data_bad);
-}
-
-// Pass 2 queued: rows from the scratch, then the exhaustive rows.
-void queue_pass2(Tree& t, const double* h, const int32_t* counts, const int64_t* offsets,
-                 int32_t* nbrs, int64_t capacity, hipStream_t st) {
-    t.timer.start(kPhPlace, st);
-    const int64_t waves = (t.n + 63) / 64;
-    unsigned grid = grid_for(waves < 1 ? 1 : waves, kWG / 64);
-    if (grid > 8192) grid = 8192;
-    hipLaunchKernelGGL(k_place, dim3(grid), dim3(kWG), 0, st, counts, t.soff.as<int64_t>(), offsets,
-                       t.scratch.as<int32_t>(), nbrs, t.n, capacity, t.ctl.as<Ctl>());
-    BT_LAUNCH();
-    t.timer.stop(kPhPlace, st);
-    hipLaunchKernelGGL((k_brute<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
-                       t.blist.as<int32_t>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), h, nullptr, offsets, t.n, capacity, nbrs,
-                       t.ctl.as<Ctl>());
+template <bool F32>
+void launch_split(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep_split<F32>), dim3(kSplitGrid), dim3(kWG), 0, st,
+                       t.split.as<Chunk>(), t.pos.as<double4>(), t.orig.as<double4>(),
+                       t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
+                       t.lrange.as<int2>(), t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
+                       t.scratch.as<int32_t>(), t.scap, t.ctl.as<Ctl>(), t.blist.as<Chunk>(),
+                       t.stats.as<Stats>());
     BT_LAUNCH();
 }
 
@@ -842,13 +851,65 @@ void find_reserve(Tree& t, int64_t entries) {
     }
 }
 
+void find_begin(Tree& t, const double* h, hipStream_t st) {
+    hipLaunchKernelGGL(k_find_reset, dim3(1), dim3(64), 0, st, t.ctl.as<Ctl>(), t.stats.as<Stats>());
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
+                       st, h, t.n, t.ctl.as<Ctl>());
+    BT_LAUNCH();
+}
+
+void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStream_t st) {
+    const unsigned g = (unsigned)std::max<int64_t>(1, grid);
+    if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true>(t, h, counts, g, st);
+    else launch_sweep<false>(t, h, counts, g, st);
+}
+
+void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
+    if (t.prm.precision == BTREE_FP32_FILTER) launch_split<true>(t, h, counts, st);
+    else launch_split<false>(t, h, counts, st);
+    hipLaunchKernelGGL((k_brute<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
+                       t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
+                       t.orig.as<double4>(), h, counts, nullptr, t.n, (int64_t)0, nullptr,
+                       t.ctl.as<Ctl>());
+    BT_LAUNCH();
+    scan_exclusive_i32(counts, offsets, t.n, t, st, &t.ctl.as<Ctl>()->data_bad);
+}
+
+void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
+                int64_t capacity, hipStream_t st) {
+    const int64_t waves = (t.n + 63) / 64;
+    unsigned grid = grid_for(waves < 1 ? 1 : waves, kWG / 64);
+    if (grid > 8192) grid = 8192;
+    hipLaunchKernelGGL(k_place, dim3(grid), dim3(kWG), 0, st, counts, t.soff.as<int64_t>(), offsets,
+                       t.scratch.as<int32_t>(), nbrs, t.n, capacity, t.ctl.as<Ctl>());
+    BT_LAUNCH();
+}
+
+void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,
+                   int64_t capacity, int64_t* totals, hipStream_t st) {
+    hipLaunchKernelGGL((k_brute<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
+                       t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
+                       t.orig.as<double4>(), h, nullptr, offsets, t.n, capacity, nbrs,
+                       t.ctl.as<Ctl>());
+    BT_LAUNCH();
+    if (totals) {
+        hipLaunchKernelGGL(k_set_totals, dim3(grid_for(t.nsets, 256)), dim3(256), 0, st, offsets,
+                           t.sets.as<SetDev>(), t.nsets, totals);
+        BT_LAUNCH();
+    }
+}
+
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
     if (t.scap == 0) find_reserve(t, std::max<int64_t>(t.n * 128, 1 << 20));
     else find_reserve(t, t.scap);
-    const unsigned grid = (unsigned)std::max<int64_t>(1, t.n_chunks);
     int64_t total = 0;
     for (int attempt = 0; attempt < 2; ++attempt) {
-        queue_pass1(t, h, counts, offsets, grid, st);
+        find_begin(t, h, st);
+        t.timer.start(kPhSweep, st);
+        find_sweep(t, h, counts, t.n_chunks, st);
+        t.timer.stop(kPhSweep, st);
+        find_counts_end(t, h, counts, offsets, st);
         BT_HIP(hipMemcpyAsync(&total, offsets + t.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
@@ -865,18 +926,10 @@ int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, 
 }
 
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs, hipStream_t st) {
-    queue_pass2(t, h, t.p1_counts, offsets, nbrs, INT64_MAX, st);
-}
-
-void find_queue(Tree& t, const double* h, int32_t* counts, int64_t* offsets, int32_t* nbrs,
-                int64_t capacity, int64_t* totals, hipStream_t st) {
-    queue_pass1(t, h, counts, offsets, (unsigned)std::max<int64_t>(1, t.chunk_cap), st);
-    queue_pass2(t, h, counts, offsets, nbrs, capacity, st);
-    if (totals) {
-        hipLaunchKernelGGL(k_set_totals, dim3(grid_for(t.nsets, 256)), dim3(256), 0, st, offsets,
-                           t.sets.as<SetDev>(), t.nsets, totals);
-        BT_LAUNCH();
-    }
+    t.timer.start(kPhPlace, st);
+    find_place(t, t.p1_counts, offsets, nbrs, INT64_MAX, st);
+    t.timer.stop(kPhPlace, st);
+    find_fill_end(t, h, offsets, nbrs, INT64_MAX, nullptr, st);
 }
 
 }  // namespace bt

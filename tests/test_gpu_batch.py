@@ -103,7 +103,7 @@ def test_graph_replays_with_new_data(prec):
     counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
     offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
     nbrs = torch.empty(cap, dtype=torch.int32, device="cuda:0")
-    with btree.Batch(sizes, precision=prec, bucket_size=32) as B:
+    with btree.Batch(sizes, precision=prec, bucket_size=32, timing=True) as B:
         for r, seed in enumerate((21, 22, 23)):
             log("replay", r, prec)
             for dst, src in zip((x, y, z, h), xs[r]):
@@ -118,6 +118,10 @@ def test_graph_replays_with_new_data(prec):
         assert st["graph_launches"] >= 3
         # one recording unless new data outgrew a pool
         assert st["graph_captures"] <= 3
+        # HIP events between graph segments time every phase of every replay
+        for k in ("build", "sweep_kernel", "place_kernel", "pass1", "pass2"):
+            assert st["phase_calls"][k] == st["graph_launches"], k
+            assert st["phase_ms"][k] > 0.0, k
 
 
 def test_pool_regrow_and_recapture():

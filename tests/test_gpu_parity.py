@@ -57,8 +57,30 @@ def test_plummer_small_full(prec):
     want = oracle.lists(x, y, z, h)
     assert_same_lists(got, want)
     # At n = 3e4 the outermost particles have 2h ~ 7 (h grows as rho^-1/3),
-    # so their work items see most of the sphere and take the exhaustive path.
-    assert got[3]["brute_chunks"] < got[3]["n_chunks"] // 20
+    # so their work items see most of the sphere: they are split, and the
+    # queries whose own box is too full take the exhaustive path.
+    assert got[3]["split_items"] > 0
+    assert got[3]["brute_chunks"] < got[3]["n"] // 100
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_split_paths(prec):
+    """Work items whose candidates overflow shared memory: a few queries with
+    a larger h make their item's box E too full (the item is re-searched in
+    groups of 8 queries), and a few with a much larger h are too full even
+    alone (exhaustive path).  Lists must still equal the oracle's."""
+    n = 20_000
+    x, y, z, h = W.uniform_cube(n, 7, 64.0)
+    h = h.copy()
+    h[::50] *= 1.6
+    h[::997] *= 3.5
+    log("split paths", prec)
+    got = gpu_lists(x, y, z, h, prec, bucket_size=64)
+    want = oracle.lists(x, y, z, h)
+    assert_same_lists(got, want)
+    st = got[3]
+    assert st["split_items"] > 0
+    assert 0 < st["brute_chunks"] <= len(h[::997])
 
 
 @pytest.mark.parametrize("name,s,kw", [("U10k", 64, {}), ("P60k", 32, {}),

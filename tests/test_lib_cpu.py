@@ -46,6 +46,11 @@ def test_struct_layouts_match_header(L, tmp_path):
     lines.append('printf("%zu\\n", sizeof(btree_stats_t));')
     for f in fields_s:
         lines.append('printf("%%zu\\n", offsetof(btree_stats_t, %s));' % f)
+    from paper_1910_02639_amd import autotune
+    fields_t = [f for f, _ in autotune.TuneSpace._fields_]
+    lines.append('printf("%zu\\n", sizeof(btree_tune_space));')
+    for f in fields_t:
+        lines.append('printf("%%zu\\n", offsetof(btree_tune_space, %s));' % f)
     lines.append("return 0;}")
     c = tmp_path / "lay.c"
     c.write_text("\n".join(lines))
@@ -55,6 +60,8 @@ def test_struct_layouts_match_header(L, tmp_path):
                                            check=True).stdout.split()]
     want = [ctypes.sizeof(L.Params)] + [getattr(L.Params, f).offset for f in fields_p]
     want += [ctypes.sizeof(L.Stats)] + [getattr(L.Stats, f).offset for f in fields_s]
+    T = autotune.TuneSpace
+    want += [ctypes.sizeof(T)] + [getattr(T, f).offset for f in fields_t]
     assert out == want
 
 
@@ -113,3 +120,70 @@ def test_product_never_imports_oracle():
             s = open(os.path.join(pkg, f)).read()
             assert not re.search(r"^\s*(import oracle|from oracle)", s, re.M), f
             assert "_oracle.so" not in s, f
+
+
+def _batch_create(L, nsets, offs, prm=None, out=True):
+    import numpy as np
+    h = ctypes.c_void_p()
+    o = np.asarray(offs, dtype=np.int64) if offs is not None else None
+    return L.lib().btree_batch_create(nsets, o.ctypes.data if o is not None else None,
+                                      prm, ctypes.byref(h) if out else None)
+
+
+def test_batch_create_rejects_bad_arguments(L):
+    """Host-side checks of btree_batch_create run before any device call."""
+    assert _batch_create(L, 2, [0, 5, 9], out=False) == L.BTREE_EINVAL
+    assert _batch_create(L, 0, [0]) == L.BTREE_EINVAL
+    assert _batch_create(L, 2, None) == L.BTREE_EINVAL
+    assert _batch_create(L, 2, [1, 5, 9]) == L.BTREE_EINVAL      # must start at 0
+    assert _batch_create(L, 2, [0, 5, 4]) == L.BTREE_EINVAL      # decreasing
+    assert _batch_create(L, 1, [0, 2 ** 31]) == L.BTREE_EINVAL   # total too large
+    arr = (L.Params * 2)(L.params(), L.params(precision="fp64"))
+    assert _batch_create(L, 2, [0, 5, 9], arr) == L.BTREE_EINVAL  # mixed precision
+    arr = (L.Params * 2)(L.params(), L.params(bucket_size=0))
+    assert _batch_create(L, 2, [0, 5, 9], arr) == L.BTREE_EINVAL
+    assert "bucket_size" in L.last_error()
+    arr = (L.Params * 2)(L.params(), L.params(timing=True))
+    assert _batch_create(L, 2, [0, 5, 9], arr) == L.BTREE_EINVAL  # mixed timing flag
+
+
+def test_batch_null_handle(L):
+    t = ctypes.c_int64()
+    assert L.lib().btree_batch_run(None, None, None, None, None, None, None, None, 0, None,
+                                   ctypes.byref(t), None) == L.BTREE_ESTATE
+    assert L.lib().btree_batch_stats(None, None) == L.BTREE_EINVAL
+    assert L.lib().btree_batch_graph_counts(None, None, None) == L.BTREE_EINVAL
+    assert L.lib().btree_batch_destroy(None) == L.BTREE_OK
+
+
+def test_tune_space_and_argument_checks(L):
+    from paper_1910_02639_amd import autotune
+    sp = autotune.space()
+    assert list(sp.bucket)[:sp.n_bucket] == [16, 24, 32, 48, 64, 96, 128, 192, 256]
+    assert list(sp.beta)[:sp.n_beta] == [0.3, 0.5, 0.8]
+    lib = autotune._lib()
+    assert lib.btree_tune_space_default(None) == L.BTREE_EINVAL
+    best = L.Params()
+    ms = ctypes.c_double()
+    P = ctypes.c_void_p(1)
+    # NULL outputs, bad space, bad bucket, NULL h: all refused on the host
+    assert lib.btree_tune(P, P, P, P, 10, None, None, None, ctypes.byref(ms), None, None) \
+        == L.BTREE_EINVAL
+    bad = autotune.space(repeats=0)
+    assert lib.btree_tune(P, P, P, P, 10, None, ctypes.byref(bad), ctypes.byref(best),
+                          ctypes.byref(ms), None, None) == L.BTREE_EINVAL
+    bad = autotune.space(buckets=[16, 0])
+    assert lib.btree_tune(P, P, P, P, 10, None, ctypes.byref(bad), ctypes.byref(best),
+                          ctypes.byref(ms), None, None) == L.BTREE_EINVAL
+    assert lib.btree_tune(P, P, P, None, 10, None, None, ctypes.byref(best),
+                          ctypes.byref(ms), None, None) == L.BTREE_EINVAL
+
+
+def test_tuner_keys():
+    import numpy as np
+    from paper_1910_02639_amd import autotune
+    assert autotune.distribution_class(np.full(100, 0.3)) == "const_h"
+    assert autotune.distribution_class(np.r_[np.zeros(5), np.full(10, 0.3)]) == "const_h"
+    assert autotune.distribution_class(np.linspace(0.1, 0.5, 10)) == "graded_h"
+    assert autotune.key(10_000, np.full(3, 1.0), "fp32") == "fp32/const_h/13"
+    assert autotune.key(2 ** 20, np.linspace(1, 2, 3), "fp64") == "fp64/graded_h/20"
