@@ -258,8 +258,10 @@ btree_status btree_tune_space_default(btree_tune_space* space);
 
 /* Times BuildTree + both FindNeighbors passes on the given particles for
  * every (s, beta) of `space` (NULL = default), other parameters from `base`
- * (NULL = defaults), with HIP events on hip_stream, and returns in *best
- * the parameters of the fastest median and in *best_ms that median.
+ * (NULL = defaults): the device time of the recorded graph of a one-set
+ * batch (HIP events around its launch on hip_stream, so host round trips
+ * of the eager path do not count), and returns in *best the parameters of
+ * the fastest median and in *best_ms that median.
  * all_ms: HOST double[n_bucket * n_beta] (row-major by bucket) or NULL.
  * Allocates its own device buffers; synchronises the stream.
  * Errors: EINVAL (bad arguments or data), ENOMEM, EDEVICE. */

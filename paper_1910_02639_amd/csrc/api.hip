@@ -284,95 +284,6 @@ btree_status btree_tune_space_default(btree_tune_space* sp) {
     return BTREE_OK;
 }
 
-btree_status btree_tune(const double* x, const double* y, const double* z, const double* h,
-                        int64_t n, const btree_params* base, const btree_tune_space* space,
-                        btree_params* best, double* best_ms, double* all_ms, void* hip_stream) {
-    return guarded([&] {
-        if (!best || !best_ms) fail(BTREE_EINVAL, "btree_tune: NULL best or best_ms");
-        btree_params prm;
-        if (base) prm = *base;
-        else btree_params_default(&prm);
-        prm.timing = 0;
-        check_params(prm);
-        btree_tune_space sp;
-        if (space) sp = *space;
-        else btree_tune_space_default(&sp);
-        if (sp.n_bucket < 1 || sp.n_bucket > 16 || sp.n_beta < 1 || sp.n_beta > 8 || sp.repeats < 1 ||
-            sp.repeats > 100)
-            fail(BTREE_EINVAL, "btree_tune: space needs 1..16 buckets, 1..8 betas, 1..100 repeats");
-        for (int k = 0; k < sp.n_bucket; ++k) {
-            btree_params q = prm;
-            q.bucket_size = sp.bucket[k];
-            check_params(q);
-            check_n(n, x, y, z, q.bucket_size);
-        }
-        for (int k = 0; k < sp.n_beta; ++k)
-            if (!std::isfinite(sp.beta[k])) fail(BTREE_EINVAL, "btree_tune: beta must be finite");
-        for (int k = 0; k < 3; ++k)
-            if (sp.reserved[k] != 0) fail(BTREE_EINVAL, "btree_tune: reserved fields must be zero");
-        if (n > 0 && !h) fail(BTREE_EINVAL, "btree_tune: h is NULL");
-        *best = prm;
-        *best_ms = 0.0;
-        if (n == 0) return;
-        hipStream_t st = static_cast<hipStream_t>(hip_stream);
-        // Outputs are the same for every candidate; one set of buffers.
-        DBuf counts, offsets, nbrs;
-        counts.reserve(sizeof(int32_t) * n);
-        offsets.reserve(sizeof(int64_t) * (n + 1));
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        BT_HIP(hipEventCreate(&e0));
-        BT_HIP(hipEventCreate(&e1));
-        btree_tree* H = new btree_tree();
-        Tree* t = &H->t;
-        if (hipGetDevice(&t->device) != hipSuccess) t->device = 0;
-        double best_t = INFINITY;
-        try {
-            for (int kb = 0; kb < sp.n_bucket; ++kb) {
-                for (int kt = 0; kt < sp.n_beta; ++kt) {
-                    t->prm = prm;
-                    t->prm.bucket_size = sp.bucket[kb];
-                    t->prm.beta = sp.beta[kt];
-                    std::vector<double> ms;
-                    for (int r = 0; r <= sp.repeats; ++r) {  // run 0 warms up
-                        BT_HIP(hipEventRecord(e0, st));
-                        do_build(t, x, y, z, n, st);
-                        t->p1_total = -1;
-                        const int64_t tot = find_pass1(*t, h, counts.as<int32_t>(),
-                                                       offsets.as<int64_t>(), st);
-                        t->p1_counts = counts.as<int32_t>();
-                        nbrs.reserve(sizeof(int32_t) * std::max<int64_t>(tot, 1));
-                        find_pass2(*t, h, offsets.as<int64_t>(), nbrs.as<int32_t>(), st);
-                        BT_HIP(hipEventRecord(e1, st));
-                        BT_HIP(hipEventSynchronize(e1));
-                        float v = 0.f;
-                        BT_HIP(hipEventElapsedTime(&v, e0, e1));
-                        if (r > 0) ms.push_back(v);
-                    }
-                    std::sort(ms.begin(), ms.end());
-                    const double med = ms[ms.size() / 2];
-                    if (all_ms) all_ms[kb * sp.n_beta + kt] = med;
-                    if (med < best_t) {
-                        best_t = med;
-                        *best = t->prm;
-                    }
-                }
-            }
-        } catch (...) {
-            (void)hipStreamSynchronize(st);
-            delete H;
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            throw;
-        }
-        delete H;
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        best->timing = base ? base->timing : 0;
-        *best_ms = best_t;
-        set_error("");
-    });
-}
-
 const char* btree_last_error(void) { return get_error(); }
 
 }  // extern "C"

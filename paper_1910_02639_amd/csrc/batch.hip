@@ -5,6 +5,7 @@
 // launches of a single tree.  The sequence is recorded as a few graph
 // segments (build, search steps) launched back to back with no host work
 // between them, so HIP events on the caller's stream can time the steps.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -27,6 +28,7 @@ struct Batch {
     int64_t launches = 0;
     int64_t captures = 0;
     std::vector<int64_t> host_tot;  // per-set totals of the last run
+    hipEvent_t e0 = nullptr, e1 = nullptr;  // around a launch, for tuning
 
     void drop_graph() {
         for (int k = 0; k < kSegs; ++k) {
@@ -40,6 +42,8 @@ struct Batch {
     ~Batch() {
         drop_graph();
         if (cs) (void)hipStreamDestroy(cs);
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
     }
 };
 
@@ -130,17 +134,83 @@ bool same_key(const Batch& B, const double* x, const double* y, const double* z,
 
 // First run: an eager build and count pass size the level count, the work
 // item bound and the scratch for this batch.
-void prime(Batch& B, const double* x, const double* y, const double* z, const double* h,
-           int32_t* counts, int64_t* offsets, hipStream_t st) {
+int64_t prime(Batch& B, const double* x, const double* y, const double* z, const double* h,
+              int32_t* counts, int64_t* offsets, hipStream_t st) {
     Tree& t = B.t;
     const bool timing = t.timer.on;
     t.timer.on = false;  // phase times count graph runs only
     build_tree(t, x, y, z, st);
     t.level_cap = std::max<int64_t>(1, std::min<int64_t>(t.levels_seen + 1, 66));
     t.chunk_cap = t.n_chunks + t.n_chunks / 4 + 64;
-    (void)find_pass1(t, h, counts, offsets, st);
+    const int64_t total = find_pass1(t, h, counts, offsets, st);
     t.timer.on = timing;
     B.primed = true;
+    return total;
+}
+
+// Runs the recorded graph once (recording it first when the pointers or
+// the capacity changed) and waits; on a pool overflow grows the pool,
+// records again and repeats.  Fills host_ctl, host_stats and host_tot.
+// With `ms`, the device time of the successful launch (HIP events around it).
+void run_graph(Batch& B, const double* x, const double* y, const double* z, const double* h,
+               int32_t* counts, int64_t* offsets, int32_t* nbrs, int64_t capacity, hipStream_t st,
+               float* ms) {
+    Tree& t = B.t;
+    if (ms && !B.e0) {
+        BT_HIP(hipEventCreate(&B.e0));
+        BT_HIP(hipEventCreate(&B.e1));
+    }
+    for (int attempt = 0;; ++attempt) {
+        if (!same_key(B, x, y, z, h, counts, offsets, nbrs, capacity))
+            capture(B, x, y, z, h, counts, offsets, nbrs, capacity);
+        if (ms) BT_HIP(hipEventRecord(B.e0, st));
+        launch(B, st);
+        if (ms) BT_HIP(hipEventRecord(B.e1, st));
+        BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(B.host_tot.data(), t.tot.p, sizeof(int64_t) * t.nsets,
+                              hipMemcpyDeviceToHost, st));
+        BT_HIP(hipStreamSynchronize(st));
+        const Ctl& c = t.host_ctl;
+        if (c.data_bad & 1) fail(BTREE_EINVAL, "btree_batch_run: non-finite particle coordinate");
+        if (c.data_bad & 2) fail(BTREE_EINVAL, "btree_batch_run: h must be finite and >= 0");
+        const int ovf = c.overflow & ~kOvfCapacity;
+        if (!ovf) break;
+        if (attempt >= 8) fail(BTREE_ENOMEM, "btree_batch_run: pools kept overflowing");
+        // Grow what was too small, then record again.
+        if (ovf & (kOvfNodes | kOvfCtab | kOvfHist)) {
+            if (ovf & kOvfNodes) t.node_cap *= 2;
+            if (ovf & kOvfCtab) t.ctab_cap *= 2;
+            if (ovf & kOvfHist) t.hist_cap *= 2;
+            plan_sets(t, t.nsets, t.set_off.data(), t.set_prm.data());
+        }
+        if (ovf & kOvfLevels) t.level_cap = std::min<int64_t>(66, 2 * t.level_cap + 1);
+        if (ovf & kOvfChunks) t.chunk_cap = (int64_t)c.n_chunks + c.n_chunks / 4 + 64;
+        if (ovf & kOvfScratch) find_reserve(t, (int64_t)c.cursor + (int64_t)(c.cursor / 16) + 1024);
+        B.drop_graph();
+    }
+    if (ms) BT_HIP(hipEventElapsedTime(ms, B.e0, B.e1));
+    const Ctl& c = t.host_ctl;
+    t.n_internal = c.n_nodes;
+    t.n_leaves = c.n_leaves;
+    t.n_chunks = c.n_chunks;
+    t.ctab_len = c.ct_len;
+    t.depth = c.depth;
+    t.max_leaf = c.max_leaf;
+    t.oversized = c.oversized;
+    t.levels_seen = c.levels;
+}
+
+// Sets a handle up for `nsets` sets (offsets on the host, validated).
+void setup(Batch& B, int32_t nsets, const int64_t* set_offsets, const btree_params* prm) {
+    Tree& t = B.t;
+    t.prm = prm[0];
+    t.timer.on = prm[0].timing != 0;
+    if (hipGetDevice(&t.device) != hipSuccess) t.device = 0;
+    BT_HIP(hipStreamCreateWithFlags(&B.cs, hipStreamNonBlocking));
+    plan_sets(t, nsets, set_offsets, prm);
+    t.level_cap = 66;
+    B.host_tot.assign((size_t)nsets, 0);
 }
 
 }  // namespace
@@ -197,15 +267,8 @@ btree_status btree_batch_create(int32_t nsets, const int64_t* set_offsets,
         }
         btree_batch* H = new btree_batch();
         Batch& B = H->b;
-        Tree& t = B.t;
         try {
-            t.prm = prm[0];
-            t.timer.on = prm[0].timing != 0;
-            if (hipGetDevice(&t.device) != hipSuccess) t.device = 0;
-            BT_HIP(hipStreamCreateWithFlags(&B.cs, hipStreamNonBlocking));
-            plan_sets(t, nsets, set_offsets, prm.data());
-            t.level_cap = 66;
-            B.host_tot.assign((size_t)nsets, 0);
+            setup(B, nsets, set_offsets, prm.data());
         } catch (...) {
             delete H;
             throw;
@@ -241,43 +304,9 @@ btree_status btree_batch_run(btree_batch_handle H, const double* x, const double
             set_error("");
             return;
         }
-        if (!B.primed) prime(B, x, y, z, h, counts, offsets, st);
-        for (int attempt = 0;; ++attempt) {
-            if (!same_key(B, x, y, z, h, counts, offsets, nbrs, capacity))
-                capture(B, x, y, z, h, counts, offsets, nbrs, capacity);
-            launch(B, st);
-            BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
-            BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
-            BT_HIP(hipMemcpyAsync(B.host_tot.data(), t.tot.p, sizeof(int64_t) * t.nsets,
-                                  hipMemcpyDeviceToHost, st));
-            BT_HIP(hipStreamSynchronize(st));
-            const Ctl& c = t.host_ctl;
-            if (c.data_bad & 1) fail(BTREE_EINVAL, "btree_batch_run: non-finite particle coordinate");
-            if (c.data_bad & 2) fail(BTREE_EINVAL, "btree_batch_run: h must be finite and >= 0");
-            const int ovf = c.overflow & ~kOvfCapacity;
-            if (!ovf) break;
-            if (attempt >= 8) fail(BTREE_ENOMEM, "btree_batch_run: pools kept overflowing");
-            // Grow what was too small, then capture again.
-            if (ovf & (kOvfNodes | kOvfCtab | kOvfHist)) {
-                if (ovf & kOvfNodes) t.node_cap *= 2;
-                if (ovf & kOvfCtab) t.ctab_cap *= 2;
-                if (ovf & kOvfHist) t.hist_cap *= 2;
-                plan_sets(t, t.nsets, t.set_off.data(), t.set_prm.data());
-            }
-            if (ovf & kOvfLevels) t.level_cap = std::min<int64_t>(66, 2 * t.level_cap + 1);
-            if (ovf & kOvfChunks) t.chunk_cap = (int64_t)c.n_chunks + c.n_chunks / 4 + 64;
-            if (ovf & kOvfScratch) find_reserve(t, (int64_t)c.cursor + (int64_t)(c.cursor / 16) + 1024);
-            B.drop_graph();
-        }
+        if (!B.primed) (void)prime(B, x, y, z, h, counts, offsets, st);
+        run_graph(B, x, y, z, h, counts, offsets, nbrs, capacity, st, nullptr);
         const Ctl& c = t.host_ctl;
-        t.n_internal = c.n_nodes;
-        t.n_leaves = c.n_leaves;
-        t.n_chunks = c.n_chunks;
-        t.ctab_len = c.ct_len;
-        t.depth = c.depth;
-        t.max_leaf = c.max_leaf;
-        t.oversized = c.oversized;
-        t.levels_seen = c.levels;
         int64_t sum = 0;
         for (int k = 0; k < t.nsets; ++k) {
             sum += B.host_tot[k];
@@ -341,6 +370,83 @@ btree_status btree_batch_destroy(btree_batch_handle H) {
     (void)hipDeviceSynchronize();
     delete H;
     return BTREE_OK;
+}
+
+btree_status btree_tune(const double* x, const double* y, const double* z, const double* h,
+                        int64_t n, const btree_params* base, const btree_tune_space* space,
+                        btree_params* best, double* best_ms, double* all_ms, void* hip_stream) {
+    return guarded_b([&] {
+        if (!best || !best_ms) fail(BTREE_EINVAL, "btree_tune: NULL best or best_ms");
+        btree_params prm;
+        if (base) prm = *base;
+        else btree_params_default(&prm);
+        prm.timing = 0;
+        check_set_params(prm, prm);
+        btree_tune_space sp;
+        if (space) sp = *space;
+        else btree_tune_space_default(&sp);
+        if (sp.n_bucket < 1 || sp.n_bucket > 16 || sp.n_beta < 1 || sp.n_beta > 8 || sp.repeats < 1 ||
+            sp.repeats > 100)
+            fail(BTREE_EINVAL, "btree_tune: space needs 1..16 buckets, 1..8 betas, 1..100 repeats");
+        if (n < 0 || n >= 0x7fffffffll) fail(BTREE_EINVAL, "btree_tune: n must be in [0, 2^31-1)");
+        for (int k = 0; k < sp.n_bucket; ++k) {
+            btree_params q = prm;
+            q.bucket_size = sp.bucket[k];
+            check_set_params(q, q);
+            if ((n + q.bucket_size - 1) / q.bucket_size > (1ll << 30))
+                fail(BTREE_EINVAL, "btree_tune: n / bucket_size must not exceed 2^30");
+        }
+        for (int k = 0; k < sp.n_beta; ++k)
+            if (!std::isfinite(sp.beta[k])) fail(BTREE_EINVAL, "btree_tune: beta must be finite");
+        for (int k = 0; k < 3; ++k)
+            if (sp.reserved[k] != 0) fail(BTREE_EINVAL, "btree_tune: reserved fields must be zero");
+        if (n > 0 && (!x || !y || !z || !h)) fail(BTREE_EINVAL, "btree_tune: NULL particle array");
+        *best = prm;
+        *best_ms = 0.0;
+        if (n == 0) {
+            set_error("");
+            return;
+        }
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        // Outputs are the same for every candidate: one set of buffers.
+        DBuf counts, offsets, nbrs;
+        counts.reserve(sizeof(int32_t) * n);
+        offsets.reserve(sizeof(int64_t) * (n + 1));
+        const int64_t off[2] = {0, n};
+        double best_t = INFINITY;
+        for (int kb = 0; kb < sp.n_bucket; ++kb) {
+            for (int kt = 0; kt < sp.n_beta; ++kt) {
+                btree_params q = prm;
+                q.bucket_size = sp.bucket[kb];
+                q.beta = sp.beta[kt];
+                // Device time of the recorded graph (build + both search
+                // passes), as the batched form runs it: no host round trips.
+                Batch B;
+                setup(B, 1, off, &q);
+                const int64_t tot = prime(B, x, y, z, h, counts.as<int32_t>(),
+                                          offsets.as<int64_t>(), st);
+                nbrs.reserve(sizeof(int32_t) * std::max<int64_t>(tot, 1));
+                const int64_t cap = (int64_t)(nbrs.bytes / sizeof(int32_t));
+                std::vector<double> ms;
+                for (int r = 0; r <= sp.repeats; ++r) {  // run 0 records the graph
+                    float v = 0.f;
+                    run_graph(B, x, y, z, h, counts.as<int32_t>(), offsets.as<int64_t>(),
+                              nbrs.as<int32_t>(), cap, st, &v);
+                    if (r > 0) ms.push_back(v);
+                }
+                std::sort(ms.begin(), ms.end());
+                const double med = ms[ms.size() / 2];
+                if (all_ms) all_ms[kb * sp.n_beta + kt] = med;
+                if (med < best_t) {
+                    best_t = med;
+                    *best = q;
+                }
+            }
+        }
+        best->timing = base ? base->timing : 0;
+        *best_ms = best_t;
+        set_error("");
+    });
 }
 
 }  // extern "C"

@@ -190,6 +190,7 @@ struct Ctl {
     uint32_t queue;             // next search work item (atomic)
     uint32_t nbrute;            // work items on the exhaustive path (atomic)
     unsigned long long cursor;  // scratch allocation (atomic)
+    uint32_t nsplit2, nsplit3;  // units left for the second and third split levels (atomic)
 };
 
 constexpr int kPersistBlocks = 2048;  // grid of the persistent per-cell / per-item kernels
@@ -267,7 +268,7 @@ struct Tree {
     DBuf lrange;   // int2 per leaf: smallest and largest original index
     DBuf chunks;   // Chunk[n_chunks]
     DBuf stats;    // Stats
-    DBuf split;    // Chunk per work item whose candidates overflowed (split further)
+    DBuf split;    // three lists of Chunk (leaf_cap each): units of the split levels
     DBuf blist;    // Chunk per query taken by the exhaustive path
     DBuf scan_tmp; // scan block sums
     DBuf scratch;  // int32 rows of the search, in work-item order

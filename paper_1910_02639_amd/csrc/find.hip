@@ -51,7 +51,6 @@ constexpr int kWaves = kWG / 64;
 constexpr int kLMax = 512;   // candidate leaves per item
 constexpr int kSMax = 256;   // walk stack entries
 constexpr int kCMax = 1536;  // staged candidates per item (both forms)
-constexpr int kMaxWords = ((kCMax / 4) + 31) / 32;  // bit words per lane and wavefront
 constexpr int kBuckets = 256;       // original-index buckets of the staged list
 constexpr int kBucketSortMax = 48;  // a fuller bucket sorts the whole item instead
 
@@ -167,10 +166,13 @@ template <> struct Ent<false> {
 
 // One work item of the sweep: walk, stage, order by original index, test,
 // rows out.  Called by every thread of the workgroup with the same item.
-// Returns false, having written nothing, when the item's candidates do not
-// fit the shared-memory budget (the caller then splits it).
-template <bool F32>
-__device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __restrict__ pos,
+// Returns 0 when done.  When the item's candidates do not fit the
+// shared-memory budget it writes nothing and returns their number (kHuge
+// when the walk itself overflowed), and the caller splits the item.
+constexpr int kHuge = 1 << 30;
+
+template <bool F32, int CMAX = kCMax, int LMAX = kLMax>
+__device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restrict__ pos,
                                            const double4* __restrict__ orig,
                                            const Node* __restrict__ nodes,
                                            const int32_t* __restrict__ ctab,
@@ -183,10 +185,11 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
                                            int32_t* __restrict__ scratch, int64_t scap,
                                            Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
     using E = typename Ent<F32>::T;
-    __shared__ E s_cand[kCMax];
+    constexpr int kMaxW = ((CMAX / kWaves) + 31) / 32;  // bit words per lane and wavefront
+    __shared__ E s_cand[CMAX];
     __shared__ int32_t s_cnt[kWaves][64];
     __shared__ int32_t s_stack[kSMax];
-    __shared__ int32_t s_leaf[kLMax];
+    __shared__ int32_t s_leaf[LMAX];
     __shared__ int32_t s_bcnt[kBuckets];
     __shared__ int32_t s_bcur[kBuckets];
     __shared__ int32_t s_qcnt[64];
@@ -311,7 +314,7 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
                 const uint64_t mi = __ballot(isi);
                 if (isl) {
                     const int p = nleaf + lanes_below(ml);
-                    if (p < kLMax) s_leaf[p] = code & ~kLeafBit;
+                    if (p < LMAX) s_leaf[p] = code & ~kLeafBit;
                 }
                 if (isi) {
                     const int p = top + lanes_below(mi);
@@ -319,7 +322,7 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
                 }
                 nleaf += __popcll(ml);
                 top += __popcll(mi);
-                if (nleaf > kLMax || top > kSMax) {
+                if (nleaf > LMAX || top > kSMax) {
                     ovf = 1;
                     break;
                 }
@@ -349,7 +352,7 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
         }
     }
     __syncthreads();
-    if (s_ovf) return false;
+    if (s_ovf) return kHuge;
     const int nleaf = __builtin_amdgcn_readfirstlane(s_nleaf);
     const int kmin = __builtin_amdgcn_readfirstlane(s_kmin);
     const int kmax = __builtin_amdgcn_readfirstlane(s_kmax);
@@ -376,7 +379,7 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
     if (lane == 0) atomicAdd(&s_C, myC);
     __syncthreads();
     const int C = __builtin_amdgcn_readfirstlane(s_C);
-    if (C > kCMax) return false;
+    if (C > CMAX) return C;
     int bstart, bcount;
     {
         int64_t tot;
@@ -391,7 +394,7 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
     if (s_big) {
         int P2 = 1;
         while (P2 < C) P2 <<= 1;
-        if (P2 > kCMax) return false;
+        if (P2 > CMAX) return C;
     }
 
     // Stage, pass 2: place each candidate in its bucket.
@@ -464,12 +467,12 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
     const int B = ((C + kWaves * 32 - 1) / (kWaves * 32)) * 32;
     const int k0 = w * B;
     const int k1 = min(k0 + B, C);
-    const int nw = (k1 > k0) ? (k1 - k0 + 31) >> 5 : 0;  // words of this wavefront, <= kMaxWords
+    const int nw = (k1 > k0) ? (k1 - k0 + 31) >> 5 : 0;  // words of this wavefront, <= kMaxW
     // The words of a lane live in registers as a shift queue: each new word
-    // enters at the top, so after nw words they sit in wq[kMaxWords - nw ..].
-    uint32_t wq[kMaxWords];
+    // enters at the top, so after nw words they sit in wq[kMaxW - nw ..].
+    uint32_t wq[kMaxW];
 #pragma unroll
-    for (int i = 0; i < kMaxWords; ++i) wq[i] = 0u;
+    for (int i = 0; i < kMaxW; ++i) wq[i] = 0u;
     int hits = 0;
     unsigned long long conf = 0;
     for (int kw = k0; kw < k1; kw += 32) {
@@ -542,8 +545,8 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
         }
         hits += __popc(word);
 #pragma unroll
-        for (int i = 0; i + 1 < kMaxWords; ++i) wq[i] = wq[i + 1];
-        wq[kMaxWords - 1] = word;
+        for (int i = 0; i + 1 < kMaxW; ++i) wq[i] = wq[i + 1];
+        wq[kMaxW - 1] = word;
     }
     if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
     s_cnt[w][lane] = hits;
@@ -573,7 +576,7 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
         // once the scratch has grown to the need the cursor now holds.
         if (t == 0) atomicOr(&ctl->overflow, kOvfScratch);
         if (w == 0 && qv) soff[qidx] = -2;
-        return true;
+        return 0;
     }
     if (w == 0 && qv) soff[qidx] = base + s_qoff[lane];
     // Rows: lane q of wavefront w writes the hits of its block right after
@@ -582,8 +585,8 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
         int64_t at = base + s_qoff[lane];
         for (int k = 0; k < w; ++k) at += s_cnt[k][lane];
 #pragma unroll
-        for (int i = 0; i < kMaxWords; ++i) {
-            const int wi = i - (kMaxWords - nw);  // word index within the block
+        for (int i = 0; i < kMaxW; ++i) {
+            const int wi = i - (kMaxW - nw);  // word index within the block
             if (wi >= 0) {
                 uint32_t word = wq[i];
                 const int kb = k0 + 32 * wi;
@@ -595,7 +598,7 @@ __device__ __forceinline__ bool sweep_item(const Chunk ch, const double4* __rest
             }
         }
     }
-    return true;
+    return 0;
 }
 
 // The sweep: workgroup g takes work item g.  The grid is the host's bound on
@@ -625,22 +628,49 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         atomicOr(&ctl->overflow, kOvfChunks);
     if (ci >= nch) return;
     const Chunk ch = chunks[ci];
-    if (!sweep_item<F32>(ch, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff, scratch,
-                         scap, ctl, stats)) {
-        if (threadIdx.x == 0) {
-            split[atomicAdd(&ctl->nsplit, 1u)] = ch;
-            atomicAdd(&stats->split, 1ull);
-        }
+    const int C = sweep_item<F32>(ch, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
+                                  scratch, scap, ctl, stats);
+    if (C && threadIdx.x == 0) {
+        split[atomicAdd(&ctl->nsplit, 1u)] = Chunk{ch.beg, ch.cnt, ch.set, C};
+        atomicAdd(&stats->split, 1ull);
     }
 }
 
 constexpr int kSubGroup = 8;  // queries per sub-item of a split work item
+// Shared-memory budget of the split kernel: it runs rarely, so it trades
+// occupancy for capacity (FP32 form 64 KB of candidates, FP64 form 96 KB).
+template <bool F32> constexpr int kCMaxSplit = F32 ? 4096 : 3072;
+constexpr int kLMaxSplit = 2048;
 
-// Work items that overflowed, cut into sub-items of kSubGroup queries (each
-// with its own, smaller box E), then into single queries; a single query
-// that still overflows takes the exhaustive path.  Persistent over the list.
-template <bool F32>
-__global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ split,
+// Lists a unit (up to 64 queries of one set) for the exhaustive path.
+__device__ __forceinline__ void to_brute(const Chunk q, const double4* __restrict__ pos,
+                                         int64_t* __restrict__ soff, Ctl* __restrict__ ctl,
+                                         Chunk* __restrict__ brute, Stats* __restrict__ stats) {
+    if (threadIdx.x < q.cnt) soff[(int)pos[q.beg + threadIdx.x].w] = -1;
+    if (threadIdx.x == 0) {
+        brute[atomicAdd(&ctl->nbrute, 1u)] = Chunk{q.beg, q.cnt, q.set, 0};
+        atomicAdd(&stats->brute, (unsigned long long)q.cnt);
+    }
+}
+
+// Work items that overflowed are searched again in three levels, each a
+// launch persistent over its list, so that the units of one item run in
+// parallel on different workgroups:
+//   level 1: the whole item, with the larger shared-memory budget;
+//   level 2: its sub-items of kSubGroup queries (each with its own box E);
+//   level 3: single queries.
+// A unit that still overflows goes to the next level, and from level 3 to
+// the exhaustive path.  In a set of at most kDenseSet particles, a unit
+// whose overflowing candidate count exceeds a quarter of the set goes to the
+// exhaustive path at once: its box covers so much of the set that a sweep
+// over the whole (small) set costs little more, and smaller boxes would
+// overflow too.  In larger sets a sweep of the whole set by one workgroup
+// would be long, so units there go down to single queries first.
+constexpr int64_t kDenseSet = 32768;
+
+template <bool F32, int LEVEL>
+__global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ in,
+                                                     Chunk* __restrict__ next,
                                                      const double4* __restrict__ pos,
                                                      const double4* __restrict__ orig,
                                                      const Node* __restrict__ nodes,
@@ -656,29 +686,34 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ s
                                                      Chunk* __restrict__ brute,
                                                      Stats* __restrict__ stats) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
-    const uint32_t ns = ctl->nsplit;
-    for (uint32_t k = blockIdx.x; k < ns; k += gridDim.x) {
-        const Chunk ch = split[k];
-        for (int q0 = 0; q0 < ch.cnt; q0 += kSubGroup) {
-            const Chunk sub{ch.beg + q0, min(kSubGroup, ch.cnt - q0), ch.set, 0};
-            __syncthreads();
-            if (sweep_item<F32>(sub, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
-                                scratch, scap, ctl, stats))
-                continue;
-            for (int q = 0; q < sub.cnt; ++q) {
-                const Chunk one{sub.beg + q, 1, ch.set, 0};
-                __syncthreads();
-                if (sweep_item<F32>(one, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts,
-                                    soff, scratch, scap, ctl, stats))
-                    continue;
-                if (threadIdx.x == 0) {
-                    brute[atomicAdd(&ctl->nbrute, 1u)] = one;
-                    soff[(int)pos[one.beg].w] = -1;
-                    atomicAdd(&stats->brute, 1ull);
-                }
-            }
+    // Units of this level: level 1 takes each listed item whole; levels 2
+    // and 3 cut each listed unit into parts of kSubGroup queries or of one.
+    constexpr int kPart = LEVEL == 1 ? kGroup : LEVEL == 2 ? kSubGroup : 1;
+    constexpr int kParts = LEVEL == 1 ? 1 : LEVEL == 2 ? kGroup / kSubGroup : kSubGroup;
+    const uint32_t nin = LEVEL == 1 ? ctl->nsplit : LEVEL == 2 ? ctl->nsplit2 : ctl->nsplit3;
+    const uint64_t units = (uint64_t)nin * kParts;
+    for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+        const Chunk src = in[u / kParts];
+        const int q0 = (int)(u % kParts) * kPart;
+        if (q0 >= src.cnt) continue;  // uniform: the unit is empty
+        const Chunk unit{src.beg + q0, min(kPart, src.cnt - q0), src.set, 0};
+        const int64_t nset = sets[unit.set].n;
+        __syncthreads();  // the previous unit is done with the shared memory
+        if (LEVEL == 1 && nset <= kDenseSet && 4 * (int64_t)src.pad > nset) {
+            to_brute(unit, pos, soff, ctl, brute, stats);
+            continue;
         }
+        const int C = sweep_item<F32, kCMaxSplit<F32>, kLMaxSplit>(
+            unit, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff, scratch, scap, ctl,
+            stats);
+        if (!C) continue;
         __syncthreads();
+        if (LEVEL == 3 || (nset <= kDenseSet && 4 * (int64_t)C > nset)) {
+            to_brute(unit, pos, soff, ctl, brute, stats);
+        } else if (threadIdx.x == 0) {
+            uint32_t* cnt = LEVEL == 1 ? &ctl->nsplit2 : &ctl->nsplit3;
+            next[atomicAdd(cnt, 1u)] = Chunk{unit.beg, unit.cnt, unit.set, C};
+        }
     }
 }
 
@@ -721,10 +756,18 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
     }
 }
 
-// Exhaustive path for the listed queries: every particle of the query's set
-// in original index order.  Persistent over the list.
+// Exhaustive path for the listed units (up to 64 queries of one set, lane q
+// of every wavefront holds query q): the set's particles, already in
+// original index order in `orig`, pass through shared memory in tiles of
+// kDenseTile; wavefront w tests its quarter of each tile with the FP64
+// predicate, one bit per (query, candidate).  Count mode sums the bits;
+// fill mode writes each row in ascending index at offsets[i] plus the hits
+// of the earlier tiles and of the lower wavefronts.  Persistent over the list.
+constexpr int kDenseTile = 768;
+constexpr int kDenseWords = kDenseTile / kWaves / 32;  // words per wavefront and tile
+
 template <int MODE>
-__global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ blist,
+__global__ __launch_bounds__(kWG) void k_dense(const Chunk* __restrict__ blist,
                                                const SetDev* __restrict__ sets,
                                                const double4* __restrict__ pos,
                                                const double4* __restrict__ orig,
@@ -733,50 +776,83 @@ __global__ __launch_bounds__(kWG) void k_brute(const Chunk* __restrict__ blist,
                                                const int64_t* __restrict__ offsets, int64_t n,
                                                int64_t capacity, int32_t* __restrict__ nbrs,
                                                Ctl* __restrict__ ctl) {
-    __shared__ int64_t sh[kWaves + 1];
+    __shared__ double4 s_c[kDenseTile];
+    __shared__ int32_t s_cnt[kWaves][64];
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     if (MODE == kFill && ((ctl->overflow & kOvfChunks) || offsets[n] > capacity)) return;
     const uint32_t nb = ctl->nbrute;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     for (uint32_t k = blockIdx.x; k < nb; k += gridDim.x) {
         const Chunk ch = blist[k];
         const int64_t jb = sets[ch.set].beg, jn = sets[ch.set].n;
-        for (int q = 0; q < ch.cnt; ++q) {
-            const double4 qp = pos[ch.beg + q];
-            const int qidx = (int)qp.w;
-            const double R = 2.0 * h[qidx];
-            int64_t run = MODE == kFill ? offsets[qidx] : 0;
-            const int64_t end = MODE == kFill ? offsets[qidx + 1] : 0;
-            int64_t mine = 0;
-            for (int64_t j0 = 0; j0 < jn; j0 += kWG) {
-                const int64_t j = j0 + t;
-                bool acc = false;
-                if (j < jn) {
-                    const double4 o = orig[jb + j];
-                    acc = p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z);
+        const bool qv = lane < ch.cnt;
+        const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const int qidx = (int)qp.w;
+        const double R = qv ? 2.0 * h[qidx] : 0.0;
+        const double r2 = qv ? __dmul_rn(R, R) : -1.0;  // nothing is below -1
+        int64_t run = (MODE == kFill && qv) ? offsets[qidx] : 0;
+        int64_t hits = 0;
+        for (int64_t t0 = 0; t0 < jn; t0 += kDenseTile) {
+            __syncthreads();  // the previous tile is no longer read
+            for (int i = t; i < kDenseTile; i += kWG) {
+                const int64_t j = t0 + i;
+                s_c[i] = j < jn ? orig[jb + j] : make_double4(NAN, NAN, NAN, 0.0);
+            }
+            __syncthreads();
+            uint32_t wd[kDenseWords];
+            int mine = 0;
+#pragma unroll
+            for (int b = 0; b < kDenseWords; ++b) {
+                uint32_t word = 0;
+                const int k0 = w * (kDenseTile / kWaves) + 32 * b;
+                for (int j = 0; j < 32; ++j) {
+                    const double4 e = s_c[k0 + j];
+                    const double dx = __dsub_rn(qp.x, e.x);
+                    const double dy = __dsub_rn(qp.y, e.y);
+                    const double dz = __dsub_rn(qp.z, e.z);
+                    push1_f64(word, __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                              __dmul_rn(dz, dz)), r2);
                 }
-                if (MODE == kCount) {
-                    mine += acc;
-                } else {
-                    const uint64_t m = __ballot(acc);
-                    if (lane == 0) sh[w] = __popcll(m);
-                    __syncthreads();
-                    int64_t before = 0, tot = 0;
-                    for (int kk = 0; kk < kWaves; ++kk) {
-                        if (kk < w) before += sh[kk];
-                        tot += sh[kk];
-                    }
-                    const int64_t at = run + before + lanes_below(m);
-                    if (acc && at < end) nbrs[at] = (int32_t)j;
-                    run += tot;
-                    __syncthreads();
-                }
+                wd[b] = word;
+                mine += __popc(word);
             }
             if (MODE == kCount) {
-                const int64_t tot = block_sum<kWG>(mine, sh);
-                if (t == 0) counts[qidx] = (int32_t)tot;
+                hits += mine;
+            } else {
+                s_cnt[w][lane] = mine;
+                __syncthreads();
+                int64_t at = run;
+                int tot = 0;
+#pragma unroll
+                for (int v = 0; v < kWaves; ++v) {
+                    const int c = s_cnt[v][lane];
+                    if (v < w) at += c;
+                    tot += c;
+                }
+                if (qv) {
+#pragma unroll
+                    for (int b = 0; b < kDenseWords; ++b) {
+                        uint32_t word = wd[b];
+                        const int64_t k0 = t0 + w * (kDenseTile / kWaves) + 32 * b;
+                        while (word) {
+                            const int j = __clz(word);
+                            word &= ~(0x80000000u >> j);
+                            nbrs[at++] = (int32_t)(k0 + j);
+                        }
+                    }
+                }
+                run += tot;
             }
         }
+        if (MODE == kCount) {
+            __syncthreads();
+            s_cnt[w][lane] = (int)hits;
+            __syncthreads();
+            if (w == 0 && qv)
+                counts[qidx] = s_cnt[0][lane] + s_cnt[1][lane] + s_cnt[2][lane] + s_cnt[3][lane];
+        }
+        __syncthreads();
     }
 }
 
@@ -785,6 +861,8 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
     if (threadIdx.x == 0) {
         ctl->queue = 0;
         ctl->nsplit = 0;
+        ctl->nsplit2 = 0;
+        ctl->nsplit3 = 0;
         ctl->nbrute = 0;
         ctl->cursor = 0;
         ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
@@ -828,15 +906,26 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipS
     BT_LAUNCH();
 }
 
-template <bool F32>
-void launch_split(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_split<F32>), dim3(kSplitGrid), dim3(kWG), 0, st,
-                       t.split.as<Chunk>(), t.pos.as<double4>(), t.orig.as<double4>(),
-                       t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
-                       t.lrange.as<int2>(), t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
+template <bool F32, int LEVEL>
+void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* in, Chunk* next,
+                        hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep_split<F32, LEVEL>), dim3(kSplitGrid), dim3(kWG), 0, st, in, next,
+                       t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
+                       t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
+                       t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.ctl.as<Ctl>(), t.blist.as<Chunk>(),
                        t.stats.as<Stats>());
     BT_LAUNCH();
+}
+
+template <bool F32>
+void launch_split(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
+    Chunk* l1 = t.split.as<Chunk>();
+    Chunk* l2 = l1 + t.leaf_cap;
+    Chunk* l3 = l2 + t.leaf_cap;
+    launch_split_level<F32, 1>(t, h, counts, l1, l2, st);
+    launch_split_level<F32, 2>(t, h, counts, l2, l3, st);
+    launch_split_level<F32, 3>(t, h, counts, l3, nullptr, st);
 }
 
 }  // namespace
@@ -868,7 +957,7 @@ void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStre
 void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
     if (t.prm.precision == BTREE_FP32_FILTER) launch_split<true>(t, h, counts, st);
     else launch_split<false>(t, h, counts, st);
-    hipLaunchKernelGGL((k_brute<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
+    hipLaunchKernelGGL((k_dense<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
                        t.orig.as<double4>(), h, counts, nullptr, t.n, (int64_t)0, nullptr,
                        t.ctl.as<Ctl>());
@@ -888,7 +977,7 @@ void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t*
 
 void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,
                    int64_t capacity, int64_t* totals, hipStream_t st) {
-    hipLaunchKernelGGL((k_brute<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
+    hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
                        t.orig.as<double4>(), h, nullptr, offsets, t.n, capacity, nbrs,
                        t.ctl.as<Ctl>());

@@ -60,15 +60,16 @@ def test_plummer_small_full(prec):
     # so their work items see most of the sphere: they are split, and the
     # queries whose own box is too full take the exhaustive path.
     assert got[3]["split_items"] > 0
-    assert got[3]["brute_chunks"] < got[3]["n"] // 100
+    assert got[3]["brute_chunks"] < got[3]["n"] // 10
 
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_split_paths(prec):
     """Work items whose candidates overflow shared memory: a few queries with
     a larger h make their item's box E too full (the item is re-searched in
-    groups of 8 queries), and a few with a much larger h are too full even
-    alone (exhaustive path).  Lists must still equal the oracle's."""
+    groups of 8 queries), and a few with a much larger h see more than a
+    quarter of this small set (their item takes the exhaustive path).  Lists
+    must still equal the oracle's."""
     n = 20_000
     x, y, z, h = W.uniform_cube(n, 7, 64.0)
     h = h.copy()
@@ -80,7 +81,7 @@ def test_split_paths(prec):
     assert_same_lists(got, want)
     st = got[3]
     assert st["split_items"] > 0
-    assert 0 < st["brute_chunks"] <= len(h[::997])
+    assert 0 < st["brute_chunks"] <= 64 * len(h[::997])
 
 
 @pytest.mark.parametrize("name,s,kw", [("U10k", 64, {}), ("P60k", 32, {}),
