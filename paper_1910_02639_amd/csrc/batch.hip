@@ -90,7 +90,10 @@ void capture(Batch& B, const double* x, const double* y, const double* z, const 
     Tree& t = B.t;
     B.drop_graph();
     record(B, kSegBuild, [&](hipStream_t s) { build_queue(t, x, y, z, (int)t.level_cap, false, s); });
-    record(B, kSegBegin, [&](hipStream_t s) { find_begin(t, h, s); });
+    record(B, kSegBegin, [&](hipStream_t s) {
+        find_begin(t, h, s);
+        find_walk(t, h, t.chunk_cap, s);
+    });
     record(B, kSegSweep, [&](hipStream_t s) { find_sweep(t, h, counts, t.chunk_cap, s); });
     record(B, kSegCounts, [&](hipStream_t s) { find_counts_end(t, h, counts, offsets, s); });
     record(B, kSegPlace, [&](hipStream_t s) { find_place(t, counts, offsets, nbrs, capacity, s); });
@@ -170,6 +173,8 @@ void run_graph(Batch& B, const double* x, const double* y, const double* z, cons
         BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
         BT_HIP(hipMemcpyAsync(B.host_tot.data(), t.tot.p, sizeof(int64_t) * t.nsets,
                               hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(t.host_stripes, t.stripes.p, sizeof t.host_stripes,
+                              hipMemcpyDeviceToHost, st));
         BT_HIP(hipStreamSynchronize(st));
         const Ctl& c = t.host_ctl;
         if (c.data_bad & 1) fail(BTREE_EINVAL, "btree_batch_run: non-finite particle coordinate");
@@ -186,7 +191,7 @@ void run_graph(Batch& B, const double* x, const double* y, const double* z, cons
         }
         if (ovf & kOvfLevels) t.level_cap = std::min<int64_t>(66, 2 * t.level_cap + 1);
         if (ovf & kOvfChunks) t.chunk_cap = (int64_t)c.n_chunks + c.n_chunks / 4 + 64;
-        if (ovf & kOvfScratch) find_reserve(t, (int64_t)c.cursor + (int64_t)(c.cursor / 16) + 1024);
+        grow_pools(t, ovf);  // also sizes the walk results for the work-item bound
         B.drop_graph();
     }
     if (ms) BT_HIP(hipEventElapsedTime(ms, B.e0, B.e1));

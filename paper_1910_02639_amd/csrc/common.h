@@ -161,7 +161,7 @@ constexpr int64_t kTileN = 8192;
 
 // Overflow bits of Ctl::overflow (a pool was too small for this input).
 enum { kOvfNodes = 1, kOvfLeaves = 2, kOvfCtab = 4, kOvfHist = 8, kOvfLevels = 16,
-       kOvfScratch = 32, kOvfCapacity = 64, kOvfChunks = 128 };
+       kOvfScratch = 32, kOvfCapacity = 64, kOvfChunks = 128, kOvfWalk = 256 };
 // A build that overflowed a pool left an incomplete tree: the search must
 // not walk it.  Work items beyond the launched grid leave counts unset: the
 // lists must not be placed.
@@ -189,9 +189,15 @@ struct Ctl {
     int32_t levels;             // levels that had cells to split
     uint32_t queue;             // next search work item (atomic)
     uint32_t nbrute;            // work items on the exhaustive path (atomic)
-    unsigned long long cursor;  // scratch allocation (atomic)
     uint32_t nsplit2, nsplit3;  // units left for the second and third split levels (atomic)
 };
+
+// Allocation from the search's pools (row scratch, walk lists) goes through
+// kStripes independent cursors, one per 128-byte line, each over its own
+// 1/kStripes of the pool: one counter shared by every workgroup of the chip
+// would serialise its atomics.
+constexpr int kStripes = 64;
+constexpr int kStripeStride = 16;  // uint64 per cursor slot
 
 constexpr int kPersistBlocks = 2048;  // grid of the persistent per-cell / per-item kernels
 
@@ -273,12 +279,18 @@ struct Tree {
     DBuf scan_tmp; // scan block sums
     DBuf scratch;  // int32 rows of the search, in work-item order
     DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)
+    DBuf stripes;  // uint64 cursors: kStripes for the scratch, then kStripes for the walk lists
+    DBuf whdr;     // int4 per work item: walk result header
+    DBuf wl;       // int2 pool: candidate leaves (first particle, count) of every item
     Work ws;
     Timer timer;
 
     int64_t n_internal = 0, n_leaves = 0, n_chunks = 0, ctab_len = 0;
     int64_t scap = 0;  // scratch capacity, entries
     int64_t chunk_cap = 0;  // work items a captured search launches for
+    int64_t wl_cap = 0;     // entries of the walk-list pool
+    int64_t wl_need = 0;    // pool size the last walk needed, when the pool was too small
+    unsigned long long host_stripes[2 * kStripes * kStripeStride] = {};
     // sets and pool capacities
     int32_t nsets = 1;
     std::vector<int64_t> set_off;        // nsets + 1, host
@@ -409,6 +421,7 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z,
 // of `capacity` entries (nothing written if they do not fit); exhaustive
 // rows and per-set totals (when `totals` is non-null).
 void find_begin(Tree& t, const double* h, hipStream_t st);
+void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st);
 void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStream_t st);
 void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st);
 void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
@@ -417,6 +430,9 @@ void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nb
                    int64_t capacity, int64_t* totals, hipStream_t st);
 // Sizes the search scratch for at least `entries` list entries.
 void find_reserve(Tree& t, int64_t entries);
+// Grows the scratch and walk-list pools from the stripe cursors in
+// t.host_stripes after a search reported these overflow bits.
+void grow_pools(Tree& t, int overflow);
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets,
                    hipStream_t st);
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,

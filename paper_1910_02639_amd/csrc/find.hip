@@ -164,6 +164,276 @@ template <> struct Ent<false> {
     __device__ static void pad(double4& e) { e.w = 4294967296.0; }
 };
 
+// Walk (Algorithm 2 with Eq. 5 applied to the box E) by one wavefront:
+// from the root code, every internal cell's sub-cell range on each axis is
+// [f(E_lo), f(E_hi)] with the build's own Eq. 2 function f (lanes 0..5
+// compute the six bounds); lanes then take one sub-cell of the range each.
+// Leaves in range go to list[0..n), internal sub-cells to the stack.
+// Returns n, or -1 when the list or the stack overflowed; kmin and kmax
+// receive the smallest and largest original index over the listed leaves.
+template <int LMAX>
+__device__ __forceinline__ int walk_wave(int32_t root_code, const double elo[3],
+                                         const double ehi[3], const Node* __restrict__ nodes,
+                                         const int32_t* __restrict__ ctab,
+                                         const int2* __restrict__ lrange,
+                                         int32_t* __restrict__ s_stack,
+                                         int32_t* __restrict__ s_leaf, int& kmin, int& kmax) {
+    const int lane = lane_id();
+    int top = 0, nleaf = 0, ovf = 0;
+    if (root_code & kLeafBit) {
+        if (lane == 0) s_leaf[0] = root_code & ~kLeafBit;
+        nleaf = 1;
+    } else {
+        if (lane == 0) s_stack[0] = root_code;
+        top = 1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    while (top > 0 && !ovf) {
+        --top;
+        const int node = __builtin_amdgcn_readfirstlane(s_stack[top]);
+        const Node N = nodes[node];
+        const int b = N.b;
+        const int ax3 = lane < 3 ? lane : lane - 3;
+        const double ev = lane == 0 ? elo[0] : lane == 1 ? elo[1] : lane == 2 ? elo[2]
+                        : lane == 3 ? ehi[0] : lane == 4 ? ehi[1] : ehi[2];
+        const double nlo = ax3 == 0 ? N.lo[0] : ax3 == 1 ? N.lo[1] : N.lo[2];
+        const double nhi = ax3 == 0 ? N.hi[0] : ax3 == 1 ? N.hi[1] : N.hi[2];
+        const int r = lane < 6 ? subcell(ev, nlo, nhi, b) : 0;
+        const int rlo0 = __shfl(r, 0, 64), rlo1 = __shfl(r, 1, 64), rlo2 = __shfl(r, 2, 64);
+        const int nx = __builtin_amdgcn_readfirstlane(__shfl(r, 3, 64) - rlo0 + 1);
+        const int ny = __builtin_amdgcn_readfirstlane(__shfl(r, 4, 64) - rlo1 + 1);
+        const int nz = __builtin_amdgcn_readfirstlane(__shfl(r, 5, 64) - rlo2 + 1);
+        const int nxy = nx * ny;
+        const int T = nxy * nz;
+        for (int k0 = 0; k0 < T; k0 += 64) {
+            const int k = k0 + lane;
+            int32_t code = kEmpty;
+            if (k < T) {
+                const int iz = k / nxy;
+                const int rem = k - iz * nxy;
+                const int iy = rem / nx;
+                const int ix = rem - iy * nx;
+                code = ctab[N.ctab + (rlo0 + ix) +
+                            (int64_t)b * ((rlo1 + iy) + (int64_t)b * (rlo2 + iz))];
+            }
+            const bool isl = code != kEmpty && (code & kLeafBit);
+            const bool isi = code != kEmpty && !(code & kLeafBit);
+            const uint64_t ml = __ballot(isl);
+            const uint64_t mi = __ballot(isi);
+            if (isl) {
+                const int p = nleaf + lanes_below(ml);
+                if (p < LMAX) s_leaf[p] = code & ~kLeafBit;
+            }
+            if (isi) {
+                const int p = top + lanes_below(mi);
+                if (p < kSMax) s_stack[p] = code;
+            }
+            nleaf += __popcll(ml);
+            top += __popcll(mi);
+            if (nleaf > LMAX || top > kSMax) {
+                ovf = 1;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    // Index range of the candidate leaves.
+    int mn = 0x7fffffff, mx = -1;
+    if (!ovf) {
+        for (int li = lane; li < nleaf; li += 64) {
+            const int2 rr = lrange[s_leaf[li]];
+            mn = min(mn, rr.x);
+            mx = max(mx, rr.y);
+        }
+    }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        mn = min(mn, __shfl_xor(mn, d, 64));
+        mx = max(mx, __shfl_xor(mx, d, 64));
+    }
+    kmin = mn;
+    kmax = mx;
+    return ovf ? -1 : nleaf;
+}
+
+// Box E of a work item (lane q holds query q, valid when qv):
+// [min fl(x_i - R_i), max fl(x_i + R_i)] per axis.
+__device__ __forceinline__ void item_box(bool qv, const double4& qp, double R, double elo[3],
+                                         double ehi[3]) {
+    const double q3[3] = {qp.x, qp.y, qp.z};
+    for (int l = 0; l < 3; ++l) {
+        elo[l] = wave_min(qv ? q3[l] - R : INFINITY);
+        ehi[l] = wave_max(qv ? q3[l] + R : -INFINITY);
+    }
+}
+
+// Stripe of a pool (scratch, walk lists) that a unit starting at sorted position `beg`
+// allocates from: a function of the unit alone, so that a search repeated
+// over the same data asks each stripe for the same amount.
+__device__ __forceinline__ int stripe_of(int beg) {
+    return (int)(((uint32_t)beg * 2654435761u) >> 26) & (kStripes - 1);
+}
+
+// The walk as a kernel of its own, one wavefront per work item, breadth
+// first: all cells of the current tree level are expanded together (lane j
+// computes the Eq. 5 ranges of frontier cell j; then the sub-cells of all
+// ranges, numbered by a prefix sum, are read from the child tables one per
+// lane), so the chain of dependent loads is two per level rather than two
+// per cell.  Result per item: a header {first entry, leaf count (negative:
+// overflow), smallest index, largest index} and the candidate leaves as
+// (first particle, count) pairs.
+constexpr int kLMaxWalk = 512;  // candidate leaves per item
+constexpr int kFMax = 128;      // cells of one frontier
+
+__global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
+                                             const double4* __restrict__ pos,
+                                             const Node* __restrict__ nodes,
+                                             const int32_t* __restrict__ ctab,
+                                             const Leaf* __restrict__ leaves,
+                                             const int2* __restrict__ lrange,
+                                             const SetDev* __restrict__ sets,
+                                             const double* __restrict__ h,
+                                             int4* __restrict__ whdr, int2* __restrict__ wl,
+                                             int64_t wl_cap, unsigned long long* __restrict__ wcur,
+                                             Ctl* __restrict__ ctl) {
+    __shared__ int32_t s_front[2][kFMax];
+    __shared__ int32_t s_pref[kFMax + 1];
+    __shared__ int64_t s_tab[kFMax];      // child-table offset of frontier cell j
+    __shared__ uint32_t s_geo[kFMax][3];  // 16-bit pairs: (b, start x), (start y, z), (size x, y)
+    __shared__ int32_t s_leaf[kLMaxWalk];
+    if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
+    const int ci = blockIdx.x;
+    if (ci >= ctl->n_chunks) return;
+    const Chunk ch = chunks[ci];
+    const int lane = threadIdx.x;
+    const bool qv = lane < ch.cnt;
+    const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+    const double R = qv ? 2.0 * h[(int)qp.w] : 0.0;
+    double elo[3], ehi[3];
+    item_box(qv, qp, R, elo, ehi);
+    const int32_t root_code = __builtin_amdgcn_readfirstlane(sets[ch.set].root);
+
+    int nleaf = 0, nf = 0, cur = 0;
+    bool ovf = false;
+    if (root_code & kLeafBit) {
+        if (lane == 0) s_leaf[0] = root_code & ~kLeafBit;
+        nleaf = 1;
+    } else {
+        if (lane == 0) s_front[0][0] = root_code;
+        nf = 1;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    while (nf > 0 && !ovf) {
+        // Ranges of the frontier cells (Eq. 5 with the build's Eq. 2).
+        int carry = 0;
+        for (int j0 = 0; j0 < nf; j0 += 64) {
+            const int j = j0 + lane;
+            int T = 0;
+            if (j < nf) {
+                const Node N = nodes[s_front[cur][j]];
+                int r[6];
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    r[l] = subcell(elo[l], N.lo[l], N.hi[l], N.b);
+                    r[3 + l] = subcell(ehi[l], N.lo[l], N.hi[l], N.b);
+                }
+                const int nx = r[3] - r[0] + 1, ny = r[4] - r[1] + 1, nz = r[5] - r[2] + 1;
+                T = nx * ny * nz;
+                s_tab[j] = N.ctab;
+                s_geo[j][0] = (uint32_t)N.b | ((uint32_t)r[0] << 16);
+                s_geo[j][1] = (uint32_t)r[1] | ((uint32_t)r[2] << 16);
+                s_geo[j][2] = (uint32_t)nx | ((uint32_t)ny << 16);
+            }
+            const int inc = wave_incl_scan(T);
+            if (j < nf) s_pref[j] = carry + inc - T;
+            carry += __shfl(inc, 63, 64);
+            if (carry > (1 << 28)) ovf = true;  // absurdly wide level: the item is split
+        }
+        if (ovf) break;
+        if (lane == 0) s_pref[nf] = carry;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // Sub-cells of all ranges, one per lane.
+        const int total = __builtin_amdgcn_readfirstlane(carry);
+        int nnext = 0;
+        for (int k0 = 0; k0 < total; k0 += 64) {
+            const int k = k0 + lane;
+            int32_t code = kEmpty;
+            if (k < total) {
+                int lo = 0, hi = nf - 1;  // frontier cell j: s_pref[j] <= k < s_pref[j + 1]
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (s_pref[mid] <= k) lo = mid;
+                    else hi = mid - 1;
+                }
+                const uint32_t g0 = s_geo[lo][0], g1 = s_geo[lo][1], g2 = s_geo[lo][2];
+                const int b = g0 & 0xffff, nx = g2 & 0xffff, nxy = nx * (int)(g2 >> 16);
+                const int e = k - s_pref[lo];
+                const int iz = e / nxy;
+                const int rem = e - iz * nxy;
+                const int iy = rem / nx;
+                const int ix = rem - iy * nx;
+                code = ctab[s_tab[lo] + ((int)(g0 >> 16) + ix) +
+                            (int64_t)b * (((int)(g1 & 0xffff) + iy) + (int64_t)b * ((int)(g1 >> 16) + iz))];
+            }
+            const bool isl = code != kEmpty && (code & kLeafBit);
+            const bool isi = code != kEmpty && !(code & kLeafBit);
+            const uint64_t ml = __ballot(isl);
+            const uint64_t mi = __ballot(isi);
+            if (isl) {
+                const int q = nleaf + lanes_below(ml);
+                if (q < kLMaxWalk) s_leaf[q] = code & ~kLeafBit;
+            }
+            if (isi) {
+                const int q = nnext + lanes_below(mi);
+                if (q < kFMax) s_front[cur ^ 1][q] = code;
+            }
+            nleaf += __popcll(ml);
+            nnext += __popcll(mi);
+            if (nleaf > kLMaxWalk || nnext > kFMax) {
+                ovf = true;
+                break;
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        cur ^= 1;
+        nf = nnext;
+    }
+    int nl = ovf ? -1 : nleaf;
+    unsigned long long off = 0;
+    if (nl > 0) {
+        const int stripe = stripe_of(ch.beg);
+        const int64_t region = wl_cap / kStripes;
+        if (lane == 0) off = atomicAdd(&wcur[stripe * kStripeStride], (unsigned long long)nl);
+        off = __shfl(off, 0, 64);
+        if ((int64_t)(off + nl) > region) {  // stripe full: the item is split, the host grows it
+            if (lane == 0) atomicOr(&ctl->overflow, kOvfWalk);
+            nl = -2;
+        }
+        off += (unsigned long long)(stripe * region);
+    }
+    int mn = 0x7fffffff, mx = -1;
+    if (nl > 0)
+        for (int li = lane; li < nl; li += 64) {
+            const int id = s_leaf[li];
+            const Leaf L = leaves[id];
+            const int2 rr = lrange[id];
+            wl[off + li] = make_int2(L.beg, L.cnt);
+            mn = min(mn, rr.x);
+            mx = max(mx, rr.y);
+        }
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) {
+        mn = min(mn, __shfl_xor(mn, d, 64));
+        mx = max(mx, __shfl_xor(mx, d, 64));
+    }
+    if (lane == 0) whdr[ci] = make_int4((int)off, nl, mn, mx);
+}
+
 // One work item of the sweep: walk, stage, order by original index, test,
 // rows out.  Called by every thread of the workgroup with the same item.
 // Returns 0 when done.  When the item's candidates do not fit the
@@ -171,8 +441,13 @@ template <> struct Ent<false> {
 // when the walk itself overflowed), and the caller splits the item.
 constexpr int kHuge = 1 << 30;
 
-template <bool F32, int CMAX = kCMax, int LMAX = kLMax>
-__device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restrict__ pos,
+constexpr int kNoCount = kHuge + 1;  // overflow of the leaf list, candidates not counted
+
+template <bool F32, bool PREWALK, int CMAX = kCMax, int LMAX = kLMax>
+__device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
+                                          const int4* __restrict__ whdr,
+                                          const int2* __restrict__ wl,
+                                          const double4* __restrict__ pos,
                                            const double4* __restrict__ orig,
                                            const Node* __restrict__ nodes,
                                            const int32_t* __restrict__ ctab,
@@ -183,16 +458,23 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
                                            int32_t* __restrict__ counts,
                                            int64_t* __restrict__ soff,
                                            int32_t* __restrict__ scratch, int64_t scap,
+                                           unsigned long long* __restrict__ scur, int stripe,
                                            Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
     using E = typename Ent<F32>::T;
     constexpr int kMaxW = ((CMAX / kWaves) + 31) / 32;  // bit words per lane and wavefront
     __shared__ E s_cand[CMAX];
     __shared__ int32_t s_cnt[kWaves][64];
-    __shared__ int32_t s_stack[kSMax];
-    __shared__ int32_t s_leaf[LMAX];
-    __shared__ int32_t s_bcnt[kBuckets];
-    __shared__ int32_t s_bcur[kBuckets];
-    __shared__ int32_t s_qcnt[64];
+    // Walk stack and candidate-leaf list; once the candidates are staged the
+    // same memory holds the permutation that orders them by original index.
+    __shared__ __align__(16) int32_t s_walk[kSMax + LMAX];
+    int32_t* const s_stack = s_walk;
+    int32_t* const s_leaf = s_walk + kSMax;
+    int2* const s_linfo = reinterpret_cast<int2*>(s_walk);  // prewalked: (first, count)
+    constexpr int kLPre = (kSMax + LMAX) / 2;
+    uint16_t* const s_perm = reinterpret_cast<uint16_t*>(s_walk);
+    static_assert(2 * (kSMax + LMAX) >= CMAX, "permutation must fit the walk area");
+    __shared__ int32_t s_bcnt[kBuckets];  // bucket sizes, then bucket starts
+    __shared__ int32_t s_bcur[kBuckets];  // placement cursors, then bucket ends
     __shared__ int32_t s_qoff[64];
     __shared__ int64_t s_scan[kWaves + 1];
     __shared__ int s_nleaf, s_ovf, s_kmin, s_kmax, s_C, s_big, s_total;
@@ -212,13 +494,7 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
 
     // Box E of the item.
     double elo[3], ehi[3];
-    {
-        const double q3[3] = {qp.x, qp.y, qp.z};
-        for (int l = 0; l < 3; ++l) {
-            elo[l] = wave_min(qv ? q3[l] - R : INFINITY);
-            ehi[l] = wave_max(qv ? q3[l] + R : -INFINITY);
-        }
-    }
+    item_box(qv, qp, R, elo, ehi);
 
     // FP32 filter set-up (derivation at the top of the file).
     float ax = 0.f, ay = 0.f, az = 0.f, tlo = -1.f, thi = -1.f;
@@ -266,93 +542,32 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
         s_big = 0;
     }
 
-    // Walk (Algorithm 2 with Eq. 5 on E), by wavefront 0.  The six range
-    // bounds of a cell are computed by lanes 0..5, one each; lanes then
-    // take one sub-cell of the range each.
-    if (w == 0) {
-        int top = 0, nleaf = 0, ovf = unsafe ? 1 : 0;
-        if (root_code & kLeafBit) {
-            if (lane == 0) s_leaf[0] = root_code & ~kLeafBit;
-            nleaf = 1;
-        } else {
-            if (lane == 0) s_stack[0] = root_code;
-            top = 1;
+    // Candidate leaves: from the walk kernel's list (PREWALK), or walked here
+    // by wavefront 0.
+    if (PREWALK) {
+        const int4 hd = whdr[ci];
+        const int nl = hd.y;
+        if (t == 0) {
+            s_nleaf = nl;
+            s_ovf = unsafe ? 1 : (nl < 0 || nl > kLPre) ? 2 : 0;
+            s_kmin = hd.z;
+            s_kmax = hd.w;
         }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        while (top > 0 && !ovf) {
-            --top;
-            const int node = __builtin_amdgcn_readfirstlane(s_stack[top]);
-            const Node N = nodes[node];
-            const int b = N.b;
-            const int ax3 = lane < 3 ? lane : lane - 3;
-            const double ev = lane == 0 ? elo[0] : lane == 1 ? elo[1] : lane == 2 ? elo[2]
-                            : lane == 3 ? ehi[0] : lane == 4 ? ehi[1] : ehi[2];
-            const double nlo = ax3 == 0 ? N.lo[0] : ax3 == 1 ? N.lo[1] : N.lo[2];
-            const double nhi = ax3 == 0 ? N.hi[0] : ax3 == 1 ? N.hi[1] : N.hi[2];
-            const int r = lane < 6 ? subcell(ev, nlo, nhi, b) : 0;
-            const int rlo0 = __shfl(r, 0, 64), rlo1 = __shfl(r, 1, 64), rlo2 = __shfl(r, 2, 64);
-            const int nx = __builtin_amdgcn_readfirstlane(__shfl(r, 3, 64) - rlo0 + 1);
-            const int ny = __builtin_amdgcn_readfirstlane(__shfl(r, 4, 64) - rlo1 + 1);
-            const int nz = __builtin_amdgcn_readfirstlane(__shfl(r, 5, 64) - rlo2 + 1);
-            const int nxy = nx * ny;
-            const int T = nxy * nz;
-            for (int k0 = 0; k0 < T; k0 += 64) {
-                const int k = k0 + lane;
-                int32_t code = kEmpty;
-                if (k < T) {
-                    const int iz = k / nxy;
-                    const int rem = k - iz * nxy;
-                    const int iy = rem / nx;
-                    const int ix = rem - iy * nx;
-                    code = ctab[N.ctab + (rlo0 + ix) +
-                                (int64_t)b * ((rlo1 + iy) + (int64_t)b * (rlo2 + iz))];
-                }
-                const bool isl = code != kEmpty && (code & kLeafBit);
-                const bool isi = code != kEmpty && !(code & kLeafBit);
-                const uint64_t ml = __ballot(isl);
-                const uint64_t mi = __ballot(isi);
-                if (isl) {
-                    const int p = nleaf + lanes_below(ml);
-                    if (p < LMAX) s_leaf[p] = code & ~kLeafBit;
-                }
-                if (isi) {
-                    const int p = top + lanes_below(mi);
-                    if (p < kSMax) s_stack[p] = code;
-                }
-                nleaf += __popcll(ml);
-                top += __popcll(mi);
-                if (nleaf > LMAX || top > kSMax) {
-                    ovf = 1;
-                    break;
-                }
-            }
-            __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-        }
-        // Index range of the candidate leaves.
-        int mn = 0x7fffffff, mx = -1;
-        if (!ovf) {
-            for (int li = lane; li < nleaf; li += 64) {
-                const int2 rr = lrange[s_leaf[li]];
-                mn = min(mn, rr.x);
-                mx = max(mx, rr.y);
-            }
-        }
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) {
-            mn = min(mn, __shfl_xor(mn, d, 64));
-            mx = max(mx, __shfl_xor(mx, d, 64));
-        }
+        if (nl >= 0 && nl <= kLPre)
+            for (int li = t; li < nl; li += kWG) s_linfo[li] = wl[hd.x + li];
+    } else if (w == 0) {
+        int mn, mx;
+        const int nl = walk_wave<LMAX>(root_code, elo, ehi, nodes, ctab, lrange, s_stack, s_leaf,
+                                       mn, mx);
         if (lane == 0) {
-            s_nleaf = nleaf;
-            s_ovf = ovf;
+            s_nleaf = nl;
+            s_ovf = (nl < 0 || unsafe) ? 1 : 0;
             s_kmin = mn;
             s_kmax = mx;
         }
     }
     __syncthreads();
-    if (s_ovf) return kHuge;
+    if (s_ovf) return s_ovf == 2 ? kNoCount : kHuge;
     const int nleaf = __builtin_amdgcn_readfirstlane(s_nleaf);
     const int kmin = __builtin_amdgcn_readfirstlane(s_kmin);
     const int kmax = __builtin_amdgcn_readfirstlane(s_kmax);
@@ -360,13 +575,20 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
     // 0..255, so sorting each bucket sorts the whole candidate list.
     const float binv = (float)kBuckets / (float)((int64_t)kmax - kmin + 1);
 
+    // (first particle, count) of candidate leaf li.
+    auto leaf_at = [&](int li) -> int2 {
+        if (PREWALK) return s_linfo[li];
+        const Leaf L = leaves[s_leaf[li]];
+        return make_int2(L.beg, L.cnt);
+    };
+
     // Stage, pass 1: count candidates inside E per index bucket.
     int myC = 0;
     for (int li = w; li < nleaf; li += kWaves) {
-        const Leaf L = leaves[s_leaf[li]];
-        for (int p0 = 0; p0 < L.cnt; p0 += 64) {
-            const bool v = p0 + lane < L.cnt;
-            const double4 P = v ? pos[L.beg + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const int2 L = leaf_at(li);
+        for (int p0 = 0; p0 < L.y; p0 += 64) {
+            const bool v = p0 + lane < L.y;
+            const double4 P = v ? pos[L.x + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
             const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
                             P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
             if (in) {
@@ -387,6 +609,8 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
         bstart = (int)block_excl_scan<kWG>(bcount, s_scan, &tot);
         s_bcur[t] = bstart;
         if (bcount > kBucketSortMax) s_big = 1;
+        __syncthreads();
+        s_bcnt[t] = bstart;
     }
     __syncthreads();
     // A crowded bucket sorts the whole list with a bitonic network padded to
@@ -399,10 +623,10 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
 
     // Stage, pass 2: place each candidate in its bucket.
     for (int li = w; li < nleaf; li += kWaves) {
-        const Leaf L = leaves[s_leaf[li]];
-        for (int p0 = 0; p0 < L.cnt; p0 += 64) {
-            const bool v = p0 + lane < L.cnt;
-            const double4 P = v ? pos[L.beg + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+        const int2 L = leaf_at(li);
+        for (int p0 = 0; p0 < L.y; p0 += 64) {
+            const bool v = p0 + lane < L.y;
+            const double4 P = v ? pos[L.x + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
             const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
                             P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
             if (in) {
@@ -419,19 +643,18 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
     }
     __syncthreads();
 
-    // Order by original index: insertion sort inside each bucket (thread b
-    // sorts bucket b); an item with a crowded bucket is sorted whole.
+    // Order by original index.  Keys are distinct, so a candidate's rank is
+    // its bucket's start plus the number of smaller keys in its bucket;
+    // s_perm[rank] = its slot (the entries themselves stay where they are).
+    // An item with a crowded bucket is sorted whole in place instead.
     if (!s_big) {
-        for (int i = 1; i < bcount; ++i) {
-            const E e = s_cand[bstart + i];
-            const int key = Ent<F32>::key(e);
-            int j = i - 1;
-            for (; j >= 0; --j) {
-                const E f = s_cand[bstart + j];
-                if (Ent<F32>::key(f) <= key) break;
-                s_cand[bstart + j + 1] = f;
-            }
-            s_cand[bstart + j + 1] = e;
+        for (int p = t; p < C; p += kWG) {
+            const int key = Ent<F32>::key(s_cand[p]);
+            const int bk = min(kBuckets - 1, (int)((float)(key - kmin) * binv));
+            const int b1 = s_bcur[bk];
+            int r = s_bcnt[bk];
+            for (int q = r; q < b1; ++q) r += Ent<F32>::key(s_cand[q]) < key;
+            s_perm[r] = (uint16_t)p;
         }
     } else {
         int P2 = 1;
@@ -454,6 +677,7 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
                 __syncthreads();
             }
         }
+        for (int p = t; p < C; p += kWG) s_perm[p] = (uint16_t)p;
     }
     __syncthreads();
 
@@ -482,9 +706,11 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
             uint32_t lword = 0;
             if (m == 32) {
                 for (int g = 0; g < 32; g += 8) {
+                    const uint4 pk = *reinterpret_cast<const uint4*>(s_perm + kw + g);
+                    const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
                     float4 e[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) e[j] = s_cand[kw + g + j];
+                    for (int j = 0; j < 8; ++j) e[j] = s_cand[(pw[j >> 1] >> (16 * (j & 1))) & 0xffffu];
                     float D[8];
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
@@ -496,7 +722,7 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
                 }
             } else {
                 for (int j = 0; j < m; ++j) {
-                    const float4 e = s_cand[kw + j];
+                    const float4 e = s_cand[s_perm[kw + j]];
                     const float tx = ax - e.x, ty = ay - e.y, tz = az - e.z;
                     push1_f32(word, lword, fmaf(tz, tz, fmaf(ty, ty, tx * tx)), tlo, thi);
                 }
@@ -510,16 +736,18 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
                 while (band) {
                     const int j = __clz(band);
                     band &= ~(0x80000000u >> j);
-                    const double4 o = orig[__float_as_int(s_cand[kw + j].w)];
+                    const double4 o = orig[__float_as_int(s_cand[s_perm[kw + j]].w)];
                     if (p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z)) word |= 0x80000000u >> j;
                 }
             }
         } else {
             if (m == 32) {
                 for (int g = 0; g < 32; g += 4) {
+                    const uint2 pk = *reinterpret_cast<const uint2*>(s_perm + kw + g);
+                    const uint32_t pw[2] = {pk.x, pk.y};
                     double4 e[4];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) e[j] = s_cand[kw + g + j];
+                    for (int j = 0; j < 4; ++j) e[j] = s_cand[(pw[j >> 1] >> (16 * (j & 1))) & 0xffffu];
                     double d2[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
@@ -533,7 +761,7 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
                 }
             } else {
                 for (int j = 0; j < m; ++j) {
-                    const double4 e = s_cand[kw + j];
+                    const double4 e = s_cand[s_perm[kw + j]];
                     const double dx = __dsub_rn(qp.x, e.x);
                     const double dy = __dsub_rn(qp.y, e.y);
                     const double dz = __dsub_rn(qp.z, e.z);
@@ -563,17 +791,19 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
         const int total = __shfl(inc, 63, 64);
         if (lane == 0) {
             s_total = total;
-            s_base = atomicAdd(&ctl->cursor, (unsigned long long)total);
+            s_base = atomicAdd(&scur[stripe * kStripeStride], (unsigned long long)total);
             atomicAdd(&stats->pair_tests, (unsigned long long)C * (unsigned long long)ch.cnt);
             atomicAdd(&stats->candidates, (unsigned long long)C);
         }
         if (qv) counts[qidx] = c;
     }
     __syncthreads();
-    const int64_t base = (int64_t)s_base;
-    if (base + s_total > scap) {
+    const int64_t region = scap / kStripes;  // this stripe's share of the scratch
+    const int64_t rbase = (int64_t)s_base;
+    const int64_t base = rbase + (int64_t)stripe * region;
+    if (rbase + s_total > region) {
         // Scratch too small this time: counts are right; the rows are redone
-        // once the scratch has grown to the need the cursor now holds.
+        // once the scratch has grown to the need the cursors now hold.
         if (t == 0) atomicOr(&ctl->overflow, kOvfScratch);
         if (w == 0 && qv) soff[qidx] = -2;
         return 0;
@@ -593,7 +823,7 @@ __device__ __forceinline__ int sweep_item(const Chunk ch, const double4* __restr
                 while (word) {
                     const int j = __clz(word);
                     word &= ~(0x80000000u >> j);
-                    scratch[at++] = Ent<F32>::key(s_cand[kb + j]) - sbeg;
+                    scratch[at++] = Ent<F32>::key(s_cand[s_perm[kb + j]]) - sbeg;
                 }
             }
         }
@@ -619,7 +849,10 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                int32_t* __restrict__ counts,
                                                int64_t* __restrict__ soff,
                                                int32_t* __restrict__ scratch, int64_t scap,
+                                               unsigned long long* __restrict__ scur,
                                                Ctl* __restrict__ ctl, Chunk* __restrict__ split,
+                                               const int4* __restrict__ whdr,
+                                               const int2* __restrict__ wl,
                                                Stats* __restrict__ stats) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     const int nch = ctl->n_chunks;
@@ -628,8 +861,9 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         atomicOr(&ctl->overflow, kOvfChunks);
     if (ci >= nch) return;
     const Chunk ch = chunks[ci];
-    const int C = sweep_item<F32>(ch, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
-                                  scratch, scap, ctl, stats);
+    const int C = sweep_item<F32, true>(ci, ch, whdr, wl, pos, orig, nodes, ctab, leaves, lrange,
+                                        sets, h, counts, soff, scratch, scap, scur,
+                                        stripe_of(ch.beg), ctl, stats);
     if (C && threadIdx.x == 0) {
         split[atomicAdd(&ctl->nsplit, 1u)] = Chunk{ch.beg, ch.cnt, ch.set, C};
         atomicAdd(&stats->split, 1ull);
@@ -682,6 +916,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
                                                      int32_t* __restrict__ counts,
                                                      int64_t* __restrict__ soff,
                                                      int32_t* __restrict__ scratch, int64_t scap,
+                                                     unsigned long long* __restrict__ scur,
                                                      Ctl* __restrict__ ctl,
                                                      Chunk* __restrict__ brute,
                                                      Stats* __restrict__ stats) {
@@ -699,16 +934,16 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         const Chunk unit{src.beg + q0, min(kPart, src.cnt - q0), src.set, 0};
         const int64_t nset = sets[unit.set].n;
         __syncthreads();  // the previous unit is done with the shared memory
-        if (LEVEL == 1 && nset <= kDenseSet && 4 * (int64_t)src.pad > nset) {
+        if (LEVEL == 1 && nset <= kDenseSet && src.pad != kNoCount && 4 * (int64_t)src.pad > nset) {
             to_brute(unit, pos, soff, ctl, brute, stats);
             continue;
         }
-        const int C = sweep_item<F32, kCMaxSplit<F32>, kLMaxSplit>(
-            unit, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff, scratch, scap, ctl,
-            stats);
+        const int C = sweep_item<F32, false, kCMaxSplit<F32>, kLMaxSplit>(
+            0, unit, nullptr, nullptr, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
+            scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
         if (!C) continue;
         __syncthreads();
-        if (LEVEL == 3 || (nset <= kDenseSet && 4 * (int64_t)C > nset)) {
+        if (LEVEL == 3 || (nset <= kDenseSet && C != kNoCount && 4 * (int64_t)C > nset)) {
             to_brute(unit, pos, soff, ctl, brute, stats);
         } else if (threadIdx.x == 0) {
             uint32_t* cnt = LEVEL == 1 ? &ctl->nsplit2 : &ctl->nsplit3;
@@ -857,16 +1092,17 @@ __global__ __launch_bounds__(kWG) void k_dense(const Chunk* __restrict__ blist,
 }
 
 // Clears the search's part of the control block and the search counters.
-__global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
+__global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
+                             unsigned long long* __restrict__ stripes) {
+    if (threadIdx.x < 2 * kStripes) stripes[threadIdx.x * kStripeStride] = 0;
     if (threadIdx.x == 0) {
         ctl->queue = 0;
         ctl->nsplit = 0;
         ctl->nsplit2 = 0;
         ctl->nsplit3 = 0;
         ctl->nbrute = 0;
-        ctl->cursor = 0;
         ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
-        ctl->overflow &= ~(kOvfScratch | kOvfCapacity | kOvfChunks);
+        ctl->overflow &= ~(kOvfScratch | kOvfCapacity | kOvfChunks | kOvfWalk);
         stats->pair_tests = 0;
         stats->confirms = 0;
         stats->brute = 0;
@@ -893,6 +1129,7 @@ __global__ void k_set_totals(const int64_t* __restrict__ offsets, const SetDev* 
 }
 
 constexpr unsigned kBruteGrid = 512;
+constexpr int64_t kWalkPerItem = 64;  // mean leaf entries per item the walk pool holds
 constexpr unsigned kSplitGrid = 1024;
 
 template <bool F32>
@@ -901,7 +1138,8 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipS
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
-                       t.scratch.as<int32_t>(), t.scap, t.ctl.as<Ctl>(), t.split.as<Chunk>(),
+                       t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
+                       t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.whdr.as<int4>(), t.wl.as<int2>(),
                        t.stats.as<Stats>());
     BT_LAUNCH();
 }
@@ -913,8 +1151,8 @@ void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* 
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
-                       t.scratch.as<int32_t>(), t.scap, t.ctl.as<Ctl>(), t.blist.as<Chunk>(),
-                       t.stats.as<Stats>());
+                       t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
+                       t.ctl.as<Ctl>(), t.blist.as<Chunk>(), t.stats.as<Stats>());
     BT_LAUNCH();
 }
 
@@ -932,6 +1170,18 @@ void launch_split(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
 
 void find_reserve(Tree& t, int64_t entries) {
     t.soff.reserve(sizeof(int64_t) * std::max<int64_t>(t.n, 1));
+    t.stripes.reserve(sizeof(unsigned long long) * 2 * kStripes * kStripeStride);
+    // Walk results: a header per work item and a pool of leaf entries (an
+    // item that does not fit the pool is searched by the split path).
+    const int64_t items = std::max<int64_t>(std::max(t.n_chunks, t.chunk_cap), 1);
+    t.whdr.reserve(sizeof(int4) * items);
+    const int64_t wl_want = std::max(kWalkPerItem * items, t.wl_need);
+    if (t.wl_cap < wl_want) {
+        t.wl.release();
+        t.wl_cap = 0;
+        t.wl.reserve(sizeof(int2) * wl_want);
+        t.wl_cap = wl_want;
+    }
     if (entries > t.scap) {
         t.scratch.release();
         t.scap = 0;
@@ -941,10 +1191,21 @@ void find_reserve(Tree& t, int64_t entries) {
 }
 
 void find_begin(Tree& t, const double* h, hipStream_t st) {
-    hipLaunchKernelGGL(k_find_reset, dim3(1), dim3(64), 0, st, t.ctl.as<Ctl>(), t.stats.as<Stats>());
+    hipLaunchKernelGGL(k_find_reset, dim3(1), dim3(2 * kStripes), 0, st, t.ctl.as<Ctl>(),
+                       t.stats.as<Stats>(), t.stripes.as<unsigned long long>());
     BT_LAUNCH();
     hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
                        st, h, t.n, t.ctl.as<Ctl>());
+    BT_LAUNCH();
+}
+
+void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st) {
+    const unsigned g = (unsigned)std::max<int64_t>(1, grid);
+    hipLaunchKernelGGL(k_walk, dim3(g), dim3(64), 0, st, t.chunks.as<Chunk>(), t.pos.as<double4>(),
+                       t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
+                       t.lrange.as<int2>(), t.sets.as<SetDev>(), h, t.whdr.as<int4>(),
+                       t.wl.as<int2>(), t.wl_cap,
+                       t.stripes.as<unsigned long long>() + kStripes * kStripeStride, t.ctl.as<Ctl>());
     BT_LAUNCH();
 }
 
@@ -989,12 +1250,26 @@ void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nb
     }
 }
 
+void grow_pools(Tree& t, int overflow) {
+    int64_t sneed = 0, wneed = 0;
+    for (int k = 0; k < kStripes; ++k) {
+        sneed = std::max<int64_t>(sneed, (int64_t)t.host_stripes[k * kStripeStride]);
+        wneed = std::max<int64_t>(wneed, (int64_t)t.host_stripes[(kStripes + k) * kStripeStride]);
+    }
+    // Every stripe gets the largest stripe's need, with room.
+    if (overflow & kOvfWalk) t.wl_need = std::max(2 * t.wl_cap, kStripes * (wneed + wneed / 4 + 64));
+    find_reserve(t, (overflow & kOvfScratch)
+                        ? std::max(t.scap + t.scap / 2, kStripes * (sneed + sneed / 8 + 1024))
+                        : t.scap);
+}
+
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
     if (t.scap == 0) find_reserve(t, std::max<int64_t>(t.n * 128, 1 << 20));
     else find_reserve(t, t.scap);
     int64_t total = 0;
-    for (int attempt = 0; attempt < 2; ++attempt) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
         find_begin(t, h, st);
+        find_walk(t, h, t.n_chunks, st);
         t.timer.start(kPhSweep, st);
         find_sweep(t, h, counts, t.n_chunks, st);
         t.timer.stop(kPhSweep, st);
@@ -1002,14 +1277,19 @@ int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, 
         BT_HIP(hipMemcpyAsync(&total, offsets + t.n, sizeof(int64_t), hipMemcpyDeviceToHost, st));
         BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(t.host_stripes, t.stripes.p, sizeof t.host_stripes,
+                              hipMemcpyDeviceToHost, st));
         BT_HIP(hipStreamSynchronize(st));
         if (t.host_ctl.data_bad & 2) fail(BTREE_EINVAL, "btree_find_neighbors: h must be finite and >= 0");
         if (t.host_ctl.overflow & kOvfChunks) fail(BTREE_EDEVICE, "btree_find_neighbors: work items out of date");
-        if (!(t.host_ctl.overflow & kOvfScratch)) break;
-        if (attempt == 1) fail(BTREE_EDEVICE, "btree_find_neighbors: scratch sizing failed");
-        // Rows did not fit: grow the scratch to the exact need and sweep again.
-        const int64_t need = (int64_t)t.host_ctl.cursor;
-        find_reserve(t, need + need / 16 + 1024);
+        if (!(t.host_ctl.overflow & (kOvfScratch | kOvfWalk))) break;
+        if (attempt == 3)
+            fail(BTREE_EDEVICE, "btree_find_neighbors: scratch sizing failed (overflow bits " +
+                                    std::to_string(t.host_ctl.overflow) + ", scratch " +
+                                    std::to_string(t.scap) + ", walk pool " +
+                                    std::to_string(t.wl_cap) + ")");
+        // Rows or walk lists did not fit: grow to the exact need, search again.
+        grow_pools(t, t.host_ctl.overflow);
     }
     return total;
 }

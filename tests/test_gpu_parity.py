@@ -305,4 +305,7 @@ def test_rebuild_reuses_handle(prec):
                           oracle.lists(xa, ya, za, ha))
         st = t.stats()
         assert st["phase_calls"]["build"] == 3 and st["phase_ms"]["build"] > 0
-        assert st["phase_calls"]["sweep_kernel"] == 3 and st["phase_calls"]["place_kernel"] == 3
+        # a pass 1 whose walk lists or rows outgrew the handle's pools runs
+        # the sweep again after growing them (never more than twice)
+        assert 3 <= st["phase_calls"]["sweep_kernel"] <= 9
+        assert st["phase_calls"]["place_kernel"] == 3
