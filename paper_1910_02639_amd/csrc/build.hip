@@ -596,6 +596,12 @@ __device__ __forceinline__ int set_of(const SetDev* __restrict__ sets, int nsets
 
 constexpr int kSortMax = 1024;  // leaves up to this size are Morton-sorted
 
+__device__ __forceinline__ uint64_t grid21(double x, double lo, double scale) {
+    const double v = (x - lo) * scale;
+    if (!(v >= 0.0)) return 0;
+    return v >= 2097151.0 ? 2097151ull : (uint64_t)v;
+}
+
 // Final pass: each leaf, Morton-sorted on its set's root box (ties by
 // original index), into the tree-ordered particle array, with the leaf's
 // smallest and largest original index.
@@ -635,20 +641,26 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
                 lrange[li] = make_int2(mn, mx);
             }
         }
-        if (L.cnt > kSortMax) {
+        // A leaf that is one work item (or too large to sort here) keeps the
+        // order of the Morton pre-sort: the order inside a work item is free.
+        if (L.cnt <= kGroup || L.cnt > kSortMax) {
             for (int k = threadIdx.x; k < L.cnt; k += kT) pos[L.beg + k] = src[L.beg + k];
             __syncthreads();
             continue;
         }
+        // 21-bit grid coordinates on the set's root box (any monotone map
+        // will do: the key only orders particles inside a leaf).
+        const double sx = (double)(1 << 21) / fmax(S.box[3] - S.box[0], 1e-300);
+        const double sy = (double)(1 << 21) / fmax(S.box[4] - S.box[1], 1e-300);
+        const double sz = (double)(1 << 21) / fmax(S.box[5] - S.box[2], 1e-300);
         int P = 1;
         while (P < L.cnt) P <<= 1;
         for (int k = threadIdx.x; k < P; k += kT) {
             if (k < L.cnt) {
                 const double4 q = src[L.beg + k];
-                const int B = 1 << 21;
-                const uint64_t kx = (uint64_t)subcell(q.x, S.box[0], S.box[3], B);
-                const uint64_t ky = (uint64_t)subcell(q.y, S.box[1], S.box[4], B);
-                const uint64_t kz = (uint64_t)subcell(q.z, S.box[2], S.box[5], B);
+                const uint64_t kx = grid21(q.x, S.box[0], sx);
+                const uint64_t ky = grid21(q.y, S.box[1], sy);
+                const uint64_t kz = grid21(q.z, S.box[2], sz);
                 key[k] = spread3_64(kx) | (spread3_64(ky) << 1) | (spread3_64(kz) << 2);
                 val[k] = (int32_t)q.w;
             } else {

@@ -952,11 +952,15 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
     }
 }
 
-// Rows from the scratch into the CSR array (original order, coalesced).  A
-// wavefront takes 64 consecutive rows; lane r first loads row r's length,
-// source and destination, then the wavefront copies the rows one by one with
-// those values broadcast from the owning lane.  Nothing is written when the
-// rows do not fit the caller's capacity.
+// Rows from the scratch into the CSR array (original order).  A wavefront
+// takes 64 consecutive rows; lane r loads row r's length, source and
+// destination, a prefix sum over the lanes numbers the entries of the 64
+// rows as one run, and every lane then copies entries e, e + 64, ... of that
+// run (four per lane per step), finding its row by a binary search over the
+// prefix held in the lanes.  So every lane moves data on every step however
+// the row lengths vary.  Rows taken by the exhaustive path (or without room
+// in the scratch) count as empty here.  Nothing is written when the rows do
+// not fit the caller's capacity.
 __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ counts,
                                                const int64_t* __restrict__ soff,
                                                const int64_t* __restrict__ offsets,
@@ -977,16 +981,36 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
         int c = 0;
         if (i < n) {
             so = soff[i];
-            c = counts[i];
             o = offsets[i];
+            c = so >= 0 ? counts[i] : 0;
         }
-        const int rows = (int)min((int64_t)64, n - r0);
-        for (int r = 0; r < rows; ++r) {
-            const int64_t rso = __shfl(so, r, 64);
-            if (rso < 0) continue;  // exhaustive path, or no room in the scratch
-            const int rc = __shfl(c, r, 64);
-            const int64_t ro = __shfl(o, r, 64);
-            for (int k = lane; k < rc; k += 64) nbrs[ro + k] = scratch[rso + k];
+        const int inc = wave_incl_scan(c);
+        const int pre = inc - c;  // first entry of row `lane` in the run
+        const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
+        for (int e0 = 0; e0 < total; e0 += 4 * 64) {
+            int64_t src[4], dst[4];
+            bool ok[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + u * 64 + lane;
+                ok[u] = e < total;
+                // row j: the last lane whose first entry is <= e
+                int j = 0;
+#pragma unroll
+                for (int step = 32; step > 0; step >>= 1) {
+                    const int cand = j + step;
+                    if (__shfl(pre, cand, 64) <= e) j = cand;
+                }
+                const int k = e - __shfl(pre, j, 64);
+                src[u] = __shfl(so, j, 64) + k;
+                dst[u] = __shfl(o, j, 64) + k;
+            }
+            int32_t v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v[u] = ok[u] ? scratch[src[u]] : 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (ok[u]) nbrs[dst[u]] = v[u];
         }
     }
 }
