@@ -50,7 +50,8 @@ def parse():
     ap.add_argument("--tune-out", default=None, help="write the cache here after tuning")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison forms")
-    ap.add_argument("--no-single", action="store_true", help="Batch64: skip the P8M block")
+    ap.add_argument("--no-single", action="store_true",
+                    help="Batch64: skip the single-set P8M and P16M blocks")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -329,6 +330,11 @@ def main():
             p8, _ = bench_single("P8M", "fp32", max(2, min(a.steps, 10)), 2, not a.no_compare,
                                  tuner)
             out["single_set_P8M"] = p8
+            p16, _ = bench_single("P16M", "fp32", max(2, min(a.steps, 5)), 1, False, tuner)
+            out["precision_form_P16M"] = {
+                k: p16[k] for k in ("n", "params", "value", "ms_per_step", "phases_ms",
+                                    "neighbours_total", "pair_tests_per_particle",
+                                    "fp64_confirmed_fraction", "exhaustive_items", "search_hbm")}
     else:
         r, xyzh = bench_single(a.workload, a.precision, a.steps, a.warmup, not a.no_compare,
                                tuner, a.bucket)

@@ -838,6 +838,7 @@ void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off_in, const btree_pa
     t.lrange.reserve(sizeof(int2) * t.leaf_cap);
     t.chunks.reserve(sizeof(Chunk) * t.leaf_cap);
     t.split.reserve(3 * sizeof(Chunk) * t.leaf_cap);
+    t.split_ci.reserve(sizeof(int32_t) * t.leaf_cap);
     t.blist.reserve(sizeof(Chunk) * t.leaf_cap);
     t.ctl.reserve(sizeof(Ctl));
     t.stats.reserve(sizeof(Stats));

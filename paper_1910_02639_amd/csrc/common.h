@@ -275,6 +275,7 @@ struct Tree {
     DBuf chunks;   // Chunk[n_chunks]
     DBuf stats;    // Stats
     DBuf split;    // three lists of Chunk (leaf_cap each): units of the split levels
+    DBuf split_ci; // int32 per entry of the first list: the work item it came from
     DBuf blist;    // Chunk per query taken by the exhaustive path
     DBuf scan_tmp; // scan block sums
     DBuf scratch;  // int32 rows of the search, in work-item order

@@ -443,7 +443,9 @@ constexpr int kHuge = 1 << 30;
 
 constexpr int kNoCount = kHuge + 1;  // overflow of the leaf list, candidates not counted
 
-template <bool F32, bool PREWALK, int CMAX = kCMax, int LMAX = kLMax>
+// WALK: 0 = walk here; 1 = take the walk kernel's list of item ci; 2 = take
+// it when ci >= 0 and the list is whole and fits, else walk here.
+template <bool F32, int WALK, int CMAX = kCMax, int LMAX = kLMax>
 __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                                           const int4* __restrict__ whdr,
                                           const int2* __restrict__ wl,
@@ -542,10 +544,12 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         s_big = 0;
     }
 
-    // Candidate leaves: from the walk kernel's list (PREWALK), or walked here
-    // by wavefront 0.
-    if (PREWALK) {
-        const int4 hd = whdr[ci];
+    // Candidate leaves: from the walk kernel's list, or walked here by
+    // wavefront 0.
+    int4 hd = make_int4(0, -1, 0, 0);
+    if (WALK != 0 && ci >= 0) hd = whdr[ci];
+    const bool pre = WALK == 1 || (WALK == 2 && hd.y >= 0 && hd.y <= kLPre);
+    if (pre) {
         const int nl = hd.y;
         if (t == 0) {
             s_nleaf = nl;
@@ -577,7 +581,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
 
     // (first particle, count) of candidate leaf li.
     auto leaf_at = [&](int li) -> int2 {
-        if (PREWALK) return s_linfo[li];
+        if (pre) return s_linfo[li];
         const Leaf L = leaves[s_leaf[li]];
         return make_int2(L.beg, L.cnt);
     };
@@ -851,6 +855,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                int32_t* __restrict__ scratch, int64_t scap,
                                                unsigned long long* __restrict__ scur,
                                                Ctl* __restrict__ ctl, Chunk* __restrict__ split,
+                                               int32_t* __restrict__ split_ci,
                                                const int4* __restrict__ whdr,
                                                const int2* __restrict__ wl,
                                                Stats* __restrict__ stats) {
@@ -861,11 +866,13 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         atomicOr(&ctl->overflow, kOvfChunks);
     if (ci >= nch) return;
     const Chunk ch = chunks[ci];
-    const int C = sweep_item<F32, true>(ci, ch, whdr, wl, pos, orig, nodes, ctab, leaves, lrange,
+    const int C = sweep_item<F32, 1>(ci, ch, whdr, wl, pos, orig, nodes, ctab, leaves, lrange,
                                         sets, h, counts, soff, scratch, scap, scur,
                                         stripe_of(ch.beg), ctl, stats);
     if (C && threadIdx.x == 0) {
-        split[atomicAdd(&ctl->nsplit, 1u)] = Chunk{ch.beg, ch.cnt, ch.set, C};
+        const uint32_t k = atomicAdd(&ctl->nsplit, 1u);
+        split[k] = Chunk{ch.beg, ch.cnt, ch.set, C};
+        split_ci[k] = ci;
         atomicAdd(&stats->split, 1ull);
     }
 }
@@ -905,6 +912,9 @@ constexpr int64_t kDenseSet = 32768;
 template <bool F32, int LEVEL>
 __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ in,
                                                      Chunk* __restrict__ next,
+                                                     const int32_t* __restrict__ split_ci,
+                                                     const int4* __restrict__ whdr,
+                                                     const int2* __restrict__ wl,
                                                      const double4* __restrict__ pos,
                                                      const double4* __restrict__ orig,
                                                      const Node* __restrict__ nodes,
@@ -938,8 +948,10 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
             to_brute(unit, pos, soff, ctl, brute, stats);
             continue;
         }
-        const int C = sweep_item<F32, false, kCMaxSplit<F32>, kLMaxSplit>(
-            0, unit, nullptr, nullptr, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
+        // Level 1 takes the item whole: its walk list, if whole, still holds.
+        const int ci = LEVEL == 1 ? split_ci[u] : -1;
+        const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit>(
+            ci, unit, whdr, wl, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
             scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
         if (!C) continue;
         __syncthreads();
@@ -1163,8 +1175,8 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipS
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
-                       t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.whdr.as<int4>(), t.wl.as<int2>(),
-                       t.stats.as<Stats>());
+                       t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.split_ci.as<int32_t>(),
+                       t.whdr.as<int4>(), t.wl.as<int2>(), t.stats.as<Stats>());
     BT_LAUNCH();
 }
 
@@ -1172,6 +1184,7 @@ template <bool F32, int LEVEL>
 void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* in, Chunk* next,
                         hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_split<F32, LEVEL>), dim3(kSplitGrid), dim3(kWG), 0, st, in, next,
+                       t.split_ci.as<int32_t>(), t.whdr.as<int4>(), t.wl.as<int2>(),
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),

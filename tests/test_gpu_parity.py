@@ -169,6 +169,26 @@ def test_plummer_8m_sampled(prec):
     assert st["brute_chunks"] == 0
 
 
+def test_plummer_16m_precision_form():
+    """The precision-form configuration: a 16M-particle Plummer sphere with
+    the FP32 filter and FP64 band confirmation.  Sampled rows (core, edge,
+    random) equal the oracle's; every entry count and offset is consistent;
+    the confirmed fraction is small but the band is exercised."""
+    x, y, z, h = W.plummer(16_000_000, 0)
+    log("P16M")
+    c, o, nb, st = gpu_lists(x, y, z, h, "fp32", bucket_size=256, beta=0.8)
+    log("P16M total", int(o[-1]), st["fp64_confirms"], st["pair_tests"])
+    check_csr_invariants(c, o, nb, len(x))
+    r = np.sqrt(x * x + y * y + z * z)
+    rng = np.random.default_rng(4)
+    core = np.argsort(r)[:16]
+    edge = np.argsort(r)[-16:]
+    rows = np.unique(np.concatenate([core, edge, rng.integers(0, len(x), 200)]))
+    want = oracle.lists(x, y, z, h, rows)
+    assert_same_lists((c, o, nb), want, rows)
+    assert 0 < st["fp64_confirms"] < st["pair_tests"] * 1e-5
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_edge_cases(prec):
     rng = np.random.default_rng(17)
