@@ -1077,13 +1077,20 @@ __global__ __launch_bounds__(kWG) void k_dense(const Chunk* __restrict__ blist,
             for (int b = 0; b < kDenseWords; ++b) {
                 uint32_t word = 0;
                 const int k0 = w * (kDenseTile / kWaves) + 32 * b;
-                for (int j = 0; j < 32; ++j) {
-                    const double4 e = s_c[k0 + j];
-                    const double dx = __dsub_rn(qp.x, e.x);
-                    const double dy = __dsub_rn(qp.y, e.y);
-                    const double dz = __dsub_rn(qp.z, e.z);
-                    push1_f64(word, __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                              __dmul_rn(dz, dz)), r2);
+                for (int g = 0; g < 32; g += 4) {
+                    double4 e[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) e[j] = s_c[k0 + g + j];
+                    double d2[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const double dx = __dsub_rn(qp.x, e[j].x);
+                        const double dy = __dsub_rn(qp.y, e[j].y);
+                        const double dz = __dsub_rn(qp.z, e[j].z);
+                        d2[j] = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                          __dmul_rn(dz, dz));
+                    }
+                    push4_f64(word, d2[0], d2[1], d2[2], d2[3], r2);
                 }
                 wd[b] = word;
                 mine += __popc(word);
