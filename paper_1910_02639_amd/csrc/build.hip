@@ -602,6 +602,39 @@ __device__ __forceinline__ uint64_t grid21(double x, double lo, double scale) {
     return v >= 2097151.0 ? 2097151ull : (uint64_t)v;
 }
 
+// Leaves of at most one work item (kGroup particles): the order inside a
+// work item is free, so such a leaf keeps the order of the Morton pre-sort.
+// One wavefront per leaf copies it into the tree-ordered array and records
+// its smallest and largest original index.
+__global__ __launch_bounds__(kT) void k_leaf_small(const Leaf* __restrict__ leaves,
+                                                   const int32_t* __restrict__ ldepth,
+                                                   const Ctl* __restrict__ ctl,
+                                                   const double4* __restrict__ P0,
+                                                   const double4* __restrict__ P1,
+                                                   double4* __restrict__ pos,
+                                                   int2* __restrict__ lrange) {
+    const int64_t nl = ctl->n_leaves;
+    const int lane = lane_id();
+    const int64_t nw = ((int64_t)gridDim.x * kT) >> 6;
+    for (int64_t li = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6; li < nl; li += nw) {
+        const Leaf L = leaves[li];
+        if (L.cnt > kGroup) continue;  // uniform over the wavefront
+        const double4* src = (ldepth[li] & 1) ? P1 : P0;
+        int mn = 0x7fffffff, mx = -1;
+        if (lane < L.cnt) {
+            const double4 q = src[L.beg + lane];
+            pos[L.beg + lane] = q;
+            mn = mx = (int)q.w;
+        }
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) {
+            mn = min(mn, __shfl_xor(mn, d, 64));
+            mx = max(mx, __shfl_xor(mx, d, 64));
+        }
+        if (lane == 0) lrange[li] = make_int2(mn, mx);
+    }
+}
+
 // Final pass: each leaf, Morton-sorted on its set's root box (ties by
 // original index), into the tree-ordered particle array, with the leaf's
 // smallest and largest original index.
@@ -620,6 +653,7 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
     const int64_t nl = ctl->n_leaves;
     for (int64_t li = blockIdx.x; li < nl; li += gridDim.x) {
         const Leaf L = leaves[li];
+        if (L.cnt <= kGroup) continue;  // done by k_leaf_small
         const double4* src = (ldepth[li] & 1) ? P1 : P0;
         const SetDev& S = sets[set_of(sets, nsets, L.beg)];
         {
@@ -641,9 +675,8 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
                 lrange[li] = make_int2(mn, mx);
             }
         }
-        // A leaf that is one work item (or too large to sort here) keeps the
-        // order of the Morton pre-sort: the order inside a work item is free.
-        if (L.cnt <= kGroup || L.cnt > kSortMax) {
+        // A leaf too large to sort here keeps the order of the Morton pre-sort.
+        if (L.cnt > kSortMax) {
             for (int k = threadIdx.x; k < L.cnt; k += kT) pos[L.beg + k] = src[L.beg + k];
             __syncthreads();
             continue;
@@ -968,6 +1001,10 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
     std::swap(t.ldepth.p, t.ldepth2.p);
     std::swap(t.ldepth.bytes, t.ldepth2.bytes);
 
+    hipLaunchKernelGGL(k_leaf_small, dim3(kPersistBlocks), dim3(kT), 0, st, t.leaves.as<Leaf>(),
+                       t.ldepth.as<int32_t>(), ctl, W.P0.as<double4>(), W.P1.as<double4>(),
+                       t.pos.as<double4>(), t.lrange.as<int2>());
+    BT_LAUNCH();
     hipLaunchKernelGGL(k_leaf_final, dim3(kPersistBlocks), dim3(kT), 0, st, t.leaves.as<Leaf>(),
                        t.ldepth.as<int32_t>(), ctl, t.sets.as<SetDev>(), t.nsets,
                        W.P0.as<double4>(), W.P1.as<double4>(), t.pos.as<double4>(),

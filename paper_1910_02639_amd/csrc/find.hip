@@ -586,22 +586,40 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         return make_int2(L.beg, L.cnt);
     };
 
-    // Stage, pass 1: count candidates inside E per index bucket.
-    int myC = 0;
-    for (int li = w; li < nleaf; li += kWaves) {
-        const int2 L = leaf_at(li);
-        for (int p0 = 0; p0 < L.y; p0 += 64) {
-            const bool v = p0 + lane < L.y;
-            const double4 P = v ? pos[L.x + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+    // Wavefront w visits the 64-particle chunks of candidate leaves w,
+    // w + kWaves, ... in order; the next chunk's load is issued before the
+    // current chunk is used, so two loads are in flight per wavefront.
+    auto visit = [&](auto&& body) {
+        int li = w, p0 = 0;
+        int2 L = li < nleaf ? leaf_at(li) : make_int2(0, 0);
+        bool vn = li < nleaf && lane < L.y;
+        double4 Pn = vn ? pos[L.x + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+        while (li < nleaf) {
+            const double4 P = Pn;
+            const bool v = vn;
+            p0 += 64;
+            if (p0 >= L.y) {
+                li += kWaves;
+                p0 = 0;
+                if (li < nleaf) L = leaf_at(li);
+            }
+            vn = li < nleaf && p0 + lane < L.y;
+            Pn = vn ? pos[L.x + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
             const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
                             P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
-            if (in) {
-                const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
-                atomicAdd(&s_bcnt[bk], 1);
-            }
-            myC += __popcll(__ballot(in));
+            body(P, in);
         }
-    }
+    };
+
+    // Stage, pass 1: count candidates inside E per index bucket.
+    int myC = 0;
+    visit([&](const double4& P, bool in) {
+        if (in) {
+            const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
+            atomicAdd(&s_bcnt[bk], 1);
+        }
+        myC += __popcll(__ballot(in));
+    });
     if (lane == 0) atomicAdd(&s_C, myC);
     __syncthreads();
     const int C = __builtin_amdgcn_readfirstlane(s_C);
@@ -626,25 +644,18 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     }
 
     // Stage, pass 2: place each candidate in its bucket.
-    for (int li = w; li < nleaf; li += kWaves) {
-        const int2 L = leaf_at(li);
-        for (int p0 = 0; p0 < L.y; p0 += 64) {
-            const bool v = p0 + lane < L.y;
-            const double4 P = v ? pos[L.x + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
-            const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
-                            P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
-            if (in) {
-                const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
-                const int slot = atomicAdd(&s_bcur[bk], 1);
-                if constexpr (F32) {
-                    s_cand[slot] = make_float4((float)(P.x - cx), (float)(P.y - cy),
-                                               (float)(P.z - cz), __int_as_float((int)P.w));
-                } else {
-                    s_cand[slot] = P;
-                }
+    visit([&](const double4& P, bool in) {
+        if (in) {
+            const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
+            const int slot = atomicAdd(&s_bcur[bk], 1);
+            if constexpr (F32) {
+                s_cand[slot] = make_float4((float)(P.x - cx), (float)(P.y - cy),
+                                           (float)(P.z - cz), __int_as_float((int)P.w));
+            } else {
+                s_cand[slot] = P;
             }
         }
-    }
+    });
     __syncthreads();
 
     // Order by original index.  Keys are distinct, so a candidate's rank is
