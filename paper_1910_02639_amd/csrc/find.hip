@@ -659,10 +659,45 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     __syncthreads();
 
     // Order by original index.  Keys are distinct, so a candidate's rank is
-    // its bucket's start plus the number of smaller keys in its bucket;
-    // s_perm[rank] = its slot (the entries themselves stay where they are).
-    // An item with a crowded bucket is sorted whole in place instead.
-    if (!s_big) {
+    // its bucket's start plus the number of smaller keys in its bucket.  With
+    // the main kernel's budget each entry then moves to its rank; with the
+    // split kernel's larger one, s_perm[rank] = its slot instead.  An item
+    // with a crowded bucket is sorted whole in place.
+    constexpr int kPer = (CMAX + kWG - 1) / kWG;
+    constexpr bool kPhys = kPer <= 6;  // the move below handles six entries per thread
+    if (!s_big && kPhys) {
+        // Entries move to their ranks through registers: all ranks are
+        // taken before any entry is overwritten.
+        // Rank of entry e from slot p (or -1 past the list).
+        auto rank_of = [&](int p, const E e) -> int {
+            const int key = Ent<F32>::key(e);
+            const int bk = min(kBuckets - 1, (int)((float)(key - kmin) * binv));
+            const int b1 = p < C ? s_bcur[bk] : 0;
+            int r = s_bcnt[bk];
+            for (int q = r; q < b1; ++q) r += Ent<F32>::key(s_cand[q]) < key;
+            return p < C ? r : -1;
+        };
+        auto at = [&](int p) -> E { return s_cand[p < C ? p : 0]; };
+        const E e0 = at(t);
+        const E e1 = at(t + kWG);
+        const E e2 = at(t + 2 * kWG);
+        const E e3 = at(t + 3 * kWG);
+        const E e4 = at(t + 4 * kWG);
+        const E e5 = at(t + 5 * kWG);
+        const int d0 = rank_of(t, e0);
+        const int d1 = rank_of(t + kWG, e1);
+        const int d2 = rank_of(t + 2 * kWG, e2);
+        const int d3 = rank_of(t + 3 * kWG, e3);
+        const int d4 = rank_of(t + 4 * kWG, e4);
+        const int d5 = rank_of(t + 5 * kWG, e5);
+        __syncthreads();
+        if (d0 >= 0) s_cand[d0] = e0;
+        if (d1 >= 0) s_cand[d1] = e1;
+        if (d2 >= 0) s_cand[d2] = e2;
+        if (d3 >= 0) s_cand[d3] = e3;
+        if (d4 >= 0) s_cand[d4] = e4;
+        if (d5 >= 0) s_cand[d5] = e5;
+    } else if (!s_big) {
         for (int p = t; p < C; p += kWG) {
             const int key = Ent<F32>::key(s_cand[p]);
             const int bk = min(kBuckets - 1, (int)((float)(key - kmin) * binv));
@@ -692,9 +727,12 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 __syncthreads();
             }
         }
-        for (int p = t; p < C; p += kWG) s_perm[p] = (uint16_t)p;
+        if (!kPhys)
+            for (int p = t; p < C; p += kWG) s_perm[p] = (uint16_t)p;
     }
     __syncthreads();
+    // Candidate k in index order.
+    auto cand = [&](int k) -> E { return kPhys ? s_cand[k] : s_cand[s_perm[k]]; };
 
     // Test: wavefront w sweeps candidates [k0, k1) (32-aligned) for its 64
     // queries; one bit per (query, candidate), first candidate in the top
@@ -721,11 +759,17 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
             uint32_t lword = 0;
             if (m == 32) {
                 for (int g = 0; g < 32; g += 8) {
-                    const uint4 pk = *reinterpret_cast<const uint4*>(s_perm + kw + g);
-                    const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
                     float4 e[8];
+                    if constexpr (kPhys) {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) e[j] = s_cand[(pw[j >> 1] >> (16 * (j & 1))) & 0xffffu];
+                        for (int j = 0; j < 8; ++j) e[j] = s_cand[kw + g + j];
+                    } else {
+                        const uint4 pk = *reinterpret_cast<const uint4*>(s_perm + kw + g);
+                        const uint32_t pw[4] = {pk.x, pk.y, pk.z, pk.w};
+#pragma unroll
+                        for (int j = 0; j < 8; ++j)
+                            e[j] = s_cand[(pw[j >> 1] >> (16 * (j & 1))) & 0xffffu];
+                    }
                     float D[8];
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
@@ -737,7 +781,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 }
             } else {
                 for (int j = 0; j < m; ++j) {
-                    const float4 e = s_cand[s_perm[kw + j]];
+                    const float4 e = cand(kw + j);
                     const float tx = ax - e.x, ty = ay - e.y, tz = az - e.z;
                     push1_f32(word, lword, fmaf(tz, tz, fmaf(ty, ty, tx * tx)), tlo, thi);
                 }
@@ -751,18 +795,24 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 while (band) {
                     const int j = __clz(band);
                     band &= ~(0x80000000u >> j);
-                    const double4 o = orig[__float_as_int(s_cand[s_perm[kw + j]].w)];
+                    const double4 o = orig[__float_as_int(cand(kw + j).w)];
                     if (p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z)) word |= 0x80000000u >> j;
                 }
             }
         } else {
             if (m == 32) {
                 for (int g = 0; g < 32; g += 4) {
-                    const uint2 pk = *reinterpret_cast<const uint2*>(s_perm + kw + g);
-                    const uint32_t pw[2] = {pk.x, pk.y};
                     double4 e[4];
+                    if constexpr (kPhys) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) e[j] = s_cand[(pw[j >> 1] >> (16 * (j & 1))) & 0xffffu];
+                        for (int j = 0; j < 4; ++j) e[j] = s_cand[kw + g + j];
+                    } else {
+                        const uint2 pk = *reinterpret_cast<const uint2*>(s_perm + kw + g);
+                        const uint32_t pw[2] = {pk.x, pk.y};
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            e[j] = s_cand[(pw[j >> 1] >> (16 * (j & 1))) & 0xffffu];
+                    }
                     double d2[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
@@ -776,7 +826,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 }
             } else {
                 for (int j = 0; j < m; ++j) {
-                    const double4 e = s_cand[s_perm[kw + j]];
+                    const double4 e = cand(kw + j);
                     const double dx = __dsub_rn(qp.x, e.x);
                     const double dy = __dsub_rn(qp.y, e.y);
                     const double dz = __dsub_rn(qp.z, e.z);
@@ -838,7 +888,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 while (word) {
                     const int j = __clz(word);
                     word &= ~(0x80000000u >> j);
-                    scratch[at++] = Ent<F32>::key(s_cand[s_perm[kb + j]]) - sbeg;
+                    scratch[at++] = Ent<F32>::key(cand(kb + j)) - sbeg;
                 }
             }
         }
