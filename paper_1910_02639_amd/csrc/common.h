@@ -281,6 +281,7 @@ struct Tree {
     DBuf scratch;  // int32 rows of the search, in work-item order
     DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)
     DBuf stripes;  // uint64 cursors: kStripes for the scratch, then kStripes for the walk lists
+    DBuf hs;       // double per particle: h in tree order (filled by each search)
     DBuf whdr;     // int4 per work item: walk result header
     DBuf wl;       // int2 pool: candidate leaves (first particle, count) of every item
     Work ws;

@@ -310,7 +310,7 @@ __global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
     const int lane = threadIdx.x;
     const bool qv = lane < ch.cnt;
     const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
-    const double R = qv ? 2.0 * h[(int)qp.w] : 0.0;
+    const double R = qv ? 2.0 * h[ch.beg + lane] : 0.0;
     double elo[3], ehi[3];
     item_box(qv, qp, R, elo, ehi);
     const int32_t root_code = __builtin_amdgcn_readfirstlane(sets[ch.set].root);
@@ -488,11 +488,19 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
 
+    // The walk kernel's list of candidate leaves, when this item has one: it
+    // does not depend on the queries, so its loads go first.
+    int4 hd = make_int4(0, -1, 0, 0);
+    if (WALK != 0 && ci >= 0) hd = whdr[ci];
+    const bool pre = WALK == 1 || (WALK == 2 && hd.y >= 0 && hd.y <= kLPre);
+    if (pre && hd.y >= 0 && hd.y <= kLPre)
+        for (int li = t; li < hd.y; li += kWG) s_linfo[li] = wl[hd.x + li];
+
     // Queries: lane q of every wavefront holds query q of the item.
     const bool qv = lane < ch.cnt;
     const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int qidx = (int)qp.w;
-    const double R = qv ? 2.0 * h[qidx] : 0.0;
+    const double R = qv ? 2.0 * h[ch.beg + lane] : 0.0;
 
     // Box E of the item.
     double elo[3], ehi[3];
@@ -544,11 +552,8 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         s_big = 0;
     }
 
-    // Candidate leaves: from the walk kernel's list, or walked here by
-    // wavefront 0.
-    int4 hd = make_int4(0, -1, 0, 0);
-    if (WALK != 0 && ci >= 0) hd = whdr[ci];
-    const bool pre = WALK == 1 || (WALK == 2 && hd.y >= 0 && hd.y <= kLPre);
+    // Candidate leaves: from the walk kernel's list (fetched at the top), or
+    // walked here by wavefront 0.
     if (pre) {
         const int nl = hd.y;
         if (t == 0) {
@@ -557,8 +562,6 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
             s_kmin = hd.z;
             s_kmax = hd.w;
         }
-        if (nl >= 0 && nl <= kLPre)
-            for (int li = t; li < nl; li += kWG) s_linfo[li] = wl[hd.x + li];
     } else if (w == 0) {
         int mn, mx;
         const int nl = walk_wave<LMAX>(root_code, elo, ehi, nodes, ctab, lrange, s_stack, s_leaf,
@@ -1121,7 +1124,7 @@ __global__ __launch_bounds__(kWG) void k_dense(const Chunk* __restrict__ blist,
         const bool qv = lane < ch.cnt;
         const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
         const int qidx = (int)qp.w;
-        const double R = qv ? 2.0 * h[qidx] : 0.0;
+        const double R = qv ? 2.0 * h[ch.beg + lane] : 0.0;
         const double r2 = qv ? __dmul_rn(R, R) : -1.0;  // nothing is below -1
         int64_t run = (MODE == kFill && qv) ? offsets[qidx] : 0;
         int64_t hits = 0;
@@ -1225,6 +1228,14 @@ __global__ void k_check_h(const double* __restrict__ h, int64_t n, Ctl* __restri
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->data_bad, 2);
 }
 
+// Smoothing lengths in tree order: hs[p] = h of the particle at position p,
+// so that a work item reads its queries' h without waiting for their index.
+__global__ void k_gather_h(const double* __restrict__ h, const double4* __restrict__ pos,
+                           int64_t n, double* __restrict__ hs) {
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) hs[p] = h[(int)pos[p].w];
+}
+
 // Lists per set: totals[k] = offsets[end of set k] - offsets[start of set k].
 __global__ void k_set_totals(const int64_t* __restrict__ offsets, const SetDev* __restrict__ sets,
                              int nsets, int64_t* __restrict__ totals) {
@@ -1241,7 +1252,7 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipS
     hipLaunchKernelGGL((k_sweep<F32>), dim3(grid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
-                       t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
+                       t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.split_ci.as<int32_t>(),
                        t.whdr.as<int4>(), t.wl.as<int2>(), t.stats.as<Stats>());
@@ -1255,7 +1266,7 @@ void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* 
                        t.split_ci.as<int32_t>(), t.whdr.as<int4>(), t.wl.as<int2>(),
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
-                       t.sets.as<SetDev>(), h, counts, t.soff.as<int64_t>(),
+                       t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.blist.as<Chunk>(), t.stats.as<Stats>());
     BT_LAUNCH();
@@ -1276,6 +1287,7 @@ void launch_split(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
 void find_reserve(Tree& t, int64_t entries) {
     t.soff.reserve(sizeof(int64_t) * std::max<int64_t>(t.n, 1));
     t.stripes.reserve(sizeof(unsigned long long) * 2 * kStripes * kStripeStride);
+    t.hs.reserve(sizeof(double) * std::max<int64_t>(t.n, 1));
     // Walk results: a header per work item and a pool of leaf entries (an
     // item that does not fit the pool is searched by the split path).
     const int64_t items = std::max<int64_t>(std::max(t.n_chunks, t.chunk_cap), 1);
@@ -1302,13 +1314,16 @@ void find_begin(Tree& t, const double* h, hipStream_t st) {
     hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
                        st, h, t.n, t.ctl.as<Ctl>());
     BT_LAUNCH();
+    hipLaunchKernelGGL(k_gather_h, dim3(grid_for(t.n, 256)), dim3(256), 0, st, h,
+                       t.pos.as<double4>(), t.n, t.hs.as<double>());
+    BT_LAUNCH();
 }
 
 void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st) {
     const unsigned g = (unsigned)std::max<int64_t>(1, grid);
     hipLaunchKernelGGL(k_walk, dim3(g), dim3(64), 0, st, t.chunks.as<Chunk>(), t.pos.as<double4>(),
                        t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
-                       t.lrange.as<int2>(), t.sets.as<SetDev>(), h, t.whdr.as<int4>(),
+                       t.lrange.as<int2>(), t.sets.as<SetDev>(), t.hs.as<double>(), t.whdr.as<int4>(),
                        t.wl.as<int2>(), t.wl_cap,
                        t.stripes.as<unsigned long long>() + kStripes * kStripeStride, t.ctl.as<Ctl>());
     BT_LAUNCH();
@@ -1325,7 +1340,7 @@ void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets
     else launch_split<false>(t, h, counts, st);
     hipLaunchKernelGGL((k_dense<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), h, counts, nullptr, t.n, (int64_t)0, nullptr,
+                       t.orig.as<double4>(), t.hs.as<double>(), counts, nullptr, t.n, (int64_t)0, nullptr,
                        t.ctl.as<Ctl>());
     BT_LAUNCH();
     scan_exclusive_i32(counts, offsets, t.n, t, st, &t.ctl.as<Ctl>()->data_bad);
@@ -1345,7 +1360,7 @@ void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nb
                    int64_t capacity, int64_t* totals, hipStream_t st) {
     hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), h, nullptr, offsets, t.n, capacity, nbrs,
+                       t.orig.as<double4>(), t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs,
                        t.ctl.as<Ctl>());
     BT_LAUNCH();
     if (totals) {
