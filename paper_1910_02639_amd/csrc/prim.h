@@ -28,22 +28,29 @@ __device__ __forceinline__ void wave_agg_inc(int32_t* counter, int64_t idx, bool
 }
 
 // Like wave_agg_inc, and returns the old value of counter[idx] plus the
-// number of lower lanes with the same idx (a unique slot per lane).
+// number of lower lanes with the same idx (a unique slot per lane).  The
+// groups of equal idx are found first (register work only), then every
+// group's first lane issues its atomic in one instruction, so the wavefront
+// waits for one atomic round trip however many groups it has.
 __device__ __forceinline__ int32_t wave_agg_slot(int32_t* counter, int64_t idx, bool active) {
     uint64_t rem = __ballot(active);
-    int32_t slot = 0;
+    int leader_of_mine = 0, rank = 0, group = 0;
     while (rem) {
         const int leader = __ffsll((unsigned long long)rem) - 1;
         const int64_t li = __shfl(idx, leader, 64);
         const bool mine = active && idx == li;
         const uint64_t peers = __ballot(mine);
-        int32_t base = 0;
-        if (lane_id() == leader) base = atomicAdd(&counter[li], (int32_t)__popcll(peers));
-        base = __shfl(base, leader, 64);
-        if (mine) slot = base + lanes_below(peers);
+        if (mine) {
+            leader_of_mine = leader;
+            rank = lanes_below(peers);
+        }
+        if (lane_id() == leader) group = __popcll(peers);
         rem &= ~peers;
     }
-    return slot;
+    int32_t base = 0;
+    if (group) base = atomicAdd(&counter[idx], (int32_t)group);
+    base = __shfl(base, leader_of_mine, 64);
+    return base + rank;
 }
 
 template <class T>
