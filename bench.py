@@ -17,7 +17,6 @@ Prints one JSON line.
 from __future__ import annotations
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -26,6 +25,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
+
+from paper_1910_02639_amd import profiling  # noqa: E402  (no GPU or HIP use)
 
 HBM_PEAK_GBS = 8000.0
 # Non-packed VALU issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-ops/s.
@@ -61,14 +62,6 @@ def log(*a):
     print("[bench %s]" % time.strftime("%H:%M:%S"), *a, file=sys.stderr, flush=True)
 
 
-def kernel_hash():
-    h = hashlib.sha256()
-    for f in ("find.hip", "common.h", "prim.h"):
-        with open(os.path.join(ROOT, "paper_1910_02639_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()[:16]
-
-
 def load_traffic(kernel, workload):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/), or
     None when absent or taken on a different kernel source."""
@@ -78,7 +71,7 @@ def load_traffic(kernel, workload):
     try:
         d = json.load(open(p))
         e = d.get(kernel, {}).get(workload)
-        if e and e.get("source_hash") == kernel_hash():
+        if e and e.get("source_hash") == profiling.source_hash():
             return e["bytes_per_launch"]
     except Exception:
         return None

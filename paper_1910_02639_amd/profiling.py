@@ -10,6 +10,9 @@ rocprofv3 byte counters, and summaries of rocprofv3 CSV output.
       COPY_WRITE_DIR --kernel k_sweep --mib 1024
       HBM bytes per dispatch of a kernel from two --pmc runs (FETCH_SIZE,
       WRITE_SIZE), each scaled by what the same counter reads for the copy.
+      With --store NAME --workload W the result is also written to
+      profiles/traffic.json under [NAME][W], with a hash of the search
+      sources so that stale figures are not reported after a kernel change.
 """
 from __future__ import annotations
 
@@ -19,6 +22,18 @@ import glob
 import json
 import os
 import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def source_hash():
+    """Hash of the search kernel sources the traffic figures belong to."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("find.hip", "common.h", "prim.h"):
+        with open(os.path.join(ROOT, "paper_1910_02639_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def copy_kernel(mib: int, reps: int):
@@ -96,14 +111,24 @@ def main(argv=None):
     t.add_argument("--kernel", default="k_sweep")
     t.add_argument("--copy-kernel", default="copy")
     t.add_argument("--mib", type=int, default=1024)
+    t.add_argument("--store", default=None, help="entry name in profiles/traffic.json")
+    t.add_argument("--workload", default=None)
     a = ap.parse_args(argv)
     if a.cmd == "copy":
         copy_kernel(a.mib, a.reps)
     elif a.cmd == "stats":
         print(stats_table(a.dir))
     else:
-        print(json.dumps(traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir,
-                                 a.kernel, a.copy_kernel, a.mib), indent=1))
+        r = traffic(a.fetch_dir, a.write_dir, a.copy_fetch_dir, a.copy_write_dir,
+                    a.kernel, a.copy_kernel, a.mib)
+        print(json.dumps(r, indent=1))
+        if a.store:
+            path = os.path.join(ROOT, "profiles", "traffic.json")
+            d = json.load(open(path)) if os.path.exists(path) else {}
+            r["source_hash"] = source_hash()
+            d.setdefault(a.store, {})[a.workload] = r
+            with open(path, "w") as fh:
+                json.dump(d, fh, indent=1)
 
 
 if __name__ == "__main__":
