@@ -300,9 +300,16 @@ def cpu_baseline_sets(sets, budget_s):
             oracle.counts(x, y, z, h, rows)
         return time.perf_counter() - t0
 
-    dt = run(64)
-    m = int(max(64, 64 * budget_s / max(dt, 1e-6)))
+    # Grow the sample until a run is long enough to extrapolate from (small
+    # runs are dominated by per-call overheads), then size it to the budget.
+    m = 64
     dt = run(m)
+    while dt < 0.25 * budget_s:
+        m = int(m * min(8.0, max(2.0, 0.5 * budget_s / max(dt, 1e-6))))
+        dt = run(m)
+    if dt < 0.75 * budget_s:
+        m = int(m * budget_s / dt)
+        dt = run(m)
     cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     return {"value": m / dt, "unit": "particles/s", "cores": cores, "kind": "oracle",
             "sample": "%d rows drawn over the %d sets (weighted by size), each tested against "
