@@ -189,14 +189,17 @@ __global__ __launch_bounds__(kT) void k_gather(const double4* __restrict__ orig,
 // Level kernels.  The cells of the level are nodes [cur_nb, cur_ne).
 // ---------------------------------------------------------------------------
 
-// Step 1: histogram size of all branching candidates of each cell.
-__global__ void k_candidates(const Node* __restrict__ nodes, const SetDev* __restrict__ sets,
+// Step 1: histogram size of all branching candidates of each cell.  The
+// cell's b field holds the first candidate (Eq. 1) until k_select replaces
+// it with the chosen one.
+__global__ void k_candidates(Node* __restrict__ nodes, const SetDev* __restrict__ sets,
                              const Ctl* __restrict__ ctl, int64_t* __restrict__ hsize) {
     const int64_t nb = ctl->cur_nb, m = ctl->lvm;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x) {
         const Node& N = nodes[nb + i];
         const int b = branching(N.n, sets[N.set].s);
+        nodes[nb + i].b = b;
         int64_t sum = 0;
         for (int bb = b;; bb = halve(bb)) {
             sum += (int64_t)bb * bb * bb;
@@ -225,49 +228,137 @@ __global__ void k_hist_check(Ctl* __restrict__ ctl, const int64_t* __restrict__ 
     }
 }
 
-// Step 2: one histogram per candidate b (Eqs. 2 and 3).  Lanes of a
-// wavefront that fall in the same sub-cell share one atomic.
+// The histogram and scatter kernels take kRunR consecutive particles per
+// workgroup.  The particles follow the Morton curve inside each cell, so
+// most of a workgroup's particles lie in one cell, its home cell (the cell of
+// the middle particle).  The home cell's bins, up to kLdsBins of them, are
+// counted in shared memory and added to global memory once per workgroup;
+// the other particles use global atomics, one per distinct bin and
+// wavefront.  Without this, the coarse bins of a large cell (b = 2: eight
+// bins for millions of particles) serialise millions of same-address
+// atomics.
+constexpr int kRunPer = 8;
+constexpr int kRunR = kT * kRunPer;
+constexpr int kLdsBins = 8192;      // scatter: int32 counters
+constexpr int kLdsHistBins = 16384;  // histogram: two 16-bit counters per word (<= kRunR each)
+static_assert(kRunR < 65536, "a workgroup's count per bin must fit 16 bits");
+
+// Adds 1 per active lane to a 16-bit counter packed two to a word in shared
+// memory.  A wavefront whose active lanes all hit one bin adds with one
+// atomic (the common case for coarse bins, where per-lane atomics would all
+// conflict on one address).
+__device__ __forceinline__ void lds_inc16(uint32_t* w, int32_t bin, bool active) {
+    const uint64_t act = __ballot(active);
+    if (!act) return;
+    const int first = __ffsll((unsigned long long)act) - 1;
+    const int32_t b0 = __shfl(bin, first, 64);
+    if (__ballot(active && bin == b0) == act) {
+        if (lane_id() == first) atomicAdd(&w[b0 >> 1], (uint32_t)__popcll(act) << ((b0 & 1) * 16));
+    } else if (active) {
+        atomicAdd(&w[bin >> 1], 1u << ((bin & 1) * 16));
+    }
+}
+
+// Rank of each active lane among the workgroup's particles of its bin, from
+// int32 counters in shared memory (one atomic when the wavefront's active
+// lanes share one bin).
+__device__ __forceinline__ int32_t lds_rank(int32_t* cnt, int32_t bin, bool active) {
+    const uint64_t act = __ballot(active);
+    if (!act) return 0;
+    const int first = __ffsll((unsigned long long)act) - 1;
+    const int32_t b0 = __shfl(bin, first, 64);
+    if (__ballot(active && bin == b0) == act) {
+        int32_t base = 0;
+        if (lane_id() == first) base = atomicAdd(&cnt[b0], (int32_t)__popcll(act));
+        base = __shfl(base, first, 64);
+        return base + lanes_below(act);
+    }
+    return active ? atomicAdd(&cnt[bin], 1) : 0;
+}
+
+// Home cell of the workgroup's range starting at `base`, or -1.
+__device__ __forceinline__ int32_t home_cell(const int32_t* __restrict__ pnode, int64_t base,
+                                             int64_t n, int32_t nb, int32_t ne) {
+    if (base >= n) return -1;
+    const int64_t mid = min(base + kRunR / 2, n - 1);
+    const int32_t h = pnode[mid];
+    return (h >= nb && h < ne) ? h : -1;
+}
+
+// Step 2: one histogram per candidate b (Eqs. 2 and 3).
 __global__ __launch_bounds__(kT) void k_histogram(const double4* __restrict__ P,
                                                   const int32_t* __restrict__ pnode, int64_t n,
                                                   const Node* __restrict__ nodes,
-                                                  const SetDev* __restrict__ sets,
                                                   const Ctl* __restrict__ ctl,
                                                   const int64_t* __restrict__ hoff,
                                                   int32_t* __restrict__ hist) {
     if (!ctl->level_ok) return;
+    __shared__ uint32_t s_bin[kLdsHistBins / 2];
     const int32_t nb = ctl->cur_nb, ne = ctl->cur_ne;
-    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-    const int32_t node = p < n ? pnode[p] : -1;
-    const bool act = node >= nb && node < ne;
-    Node N;
-    double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
-    int bb = 2, ncand = 0;
-    int64_t off = 0;
-    if (act) {
-        N = nodes[node];
-        q = P[p];
-        off = hoff[node - nb];
-        bb = branching(N.n, sets[N.set].s);
-        for (int b = bb;; b = halve(b)) {
-            ++ncand;
-            if (b == 2) break;
+    const int64_t base = (int64_t)blockIdx.x * kRunR;
+    // Shared window: the last kLdsHistBins bins of the home cell's
+    // candidates (the small b, whose bins are the crowded ones).
+    const int32_t home = home_cell(pnode, base, n, nb, ne);
+    int64_t wlo = 0;
+    int32_t wlen = 0;
+    if (home >= 0) {
+        const int64_t h0 = hoff[home - nb], h1 = hoff[home - nb + 1];
+        wlo = max(h0, h1 - kLdsHistBins);
+        wlen = (int32_t)(h1 - wlo);
+    }
+    const int32_t wwords = (wlen + 1) >> 1;
+    for (int i = threadIdx.x; i < wwords; i += kT) s_bin[i] = 0;
+    __syncthreads();
+    int32_t node[kRunPer];
+#pragma unroll
+    for (int j = 0; j < kRunPer; ++j) {
+        const int64_t p = base + j * kT + threadIdx.x;
+        node[j] = p < n ? pnode[p] : -1;
+    }
+#pragma unroll 1
+    for (int j = 0; j < kRunPer; ++j) {
+        const int64_t p = base + j * kT + threadIdx.x;
+        const bool act = node[j] >= nb && node[j] < ne;
+        double tx = 0.0, ty = 0.0, tz = 0.0;
+        int64_t off = 0;
+        int bb = 2, ncand = 0;
+        if (act) {
+            const double4 q = P[p];
+            const Node& N = nodes[node[j]];
+            // Eq. 2 fractions per axis: the same for every candidate b.
+            tx = subcell_frac(q.x, N.lo[0], N.hi[0]);
+            ty = subcell_frac(q.y, N.lo[1], N.hi[1]);
+            tz = subcell_frac(q.z, N.lo[2], N.hi[2]);
+            off = hoff[node[j] - nb];
+            bb = N.b;  // Eq. 1, set by k_candidates
+            for (int b = bb;; b = halve(b)) {
+                ++ncand;
+                if (b == 2) break;
+            }
+        }
+        const bool mine = act && node[j] == home;
+        int maxc = ncand;
+#pragma unroll
+        for (int d = 32; d > 0; d >>= 1) maxc = max(maxc, __shfl_xor(maxc, d, 64));
+        for (int k = 0; k < maxc; ++k) {
+            const bool a = act && k < ncand;
+            int64_t key = 0;
+            if (a) {
+                key = off + subcell_of(tx, bb) +
+                      (int64_t)bb * (subcell_of(ty, bb) + (int64_t)bb * subcell_of(tz, bb));
+                off += (int64_t)bb * bb * bb;
+                bb = halve(bb);
+            }
+            const bool local = a && mine && key >= wlo;
+            lds_inc16(s_bin, (int32_t)(key - wlo), local);
+            wave_agg_inc(hist, key, a && !local);
         }
     }
-    int maxc = ncand;
-#pragma unroll
-    for (int d = 32; d > 0; d >>= 1) maxc = max(maxc, __shfl_xor(maxc, d, 64));
-    for (int k = 0; k < maxc; ++k) {
-        const bool a = act && k < ncand;
-        int64_t bin = 0;
-        if (a) {
-            const int cx = subcell(q.x, N.lo[0], N.hi[0], bb);
-            const int cy = subcell(q.y, N.lo[1], N.hi[1], bb);
-            const int cz = subcell(q.z, N.lo[2], N.hi[2], bb);
-            bin = off + cx + (int64_t)bb * (cy + (int64_t)bb * cz);
-            off += (int64_t)bb * bb * bb;
-            bb = halve(bb);
-        }
-        wave_agg_inc(hist, bin, a);
+    __syncthreads();
+    for (int i = threadIdx.x; i < wwords; i += kT) {
+        const uint32_t v = s_bin[i];
+        if (v & 0xffffu) atomicAdd(&hist[wlo + 2 * i], (int32_t)(v & 0xffffu));
+        if (v >> 16) atomicAdd(&hist[wlo + 2 * i + 1], (int32_t)(v >> 16));
     }
 }
 
@@ -483,8 +574,11 @@ __global__ __launch_bounds__(kT) void k_emit(Node* __restrict__ nodes,
     }
 }
 
-// Step 5: scatter each particle of a cell into its sub-cell segment (slots
-// handed out per wavefront and sub-cell).
+// Step 5: scatter each particle of a cell into its sub-cell segment.  Home
+// cell particles (when the cell's b^3 fits kLdsBins) take a rank in their
+// sub-cell from shared counters, and each sub-cell reserves its slots for
+// the workgroup with one global atomic; the others take slots per wavefront
+// and sub-cell.
 __global__ __launch_bounds__(kT) void k_scatter(const double4* __restrict__ Psrc,
                                                 double4* __restrict__ Pdst,
                                                 const int32_t* __restrict__ pn_src,
@@ -497,31 +591,74 @@ __global__ __launch_bounds__(kT) void k_scatter(const double4* __restrict__ Psrc
                                                 int32_t* __restrict__ cursor,
                                                 const int32_t* __restrict__ ctab) {
     if (!ctl->level_ok) return;
+    __shared__ int32_t s_cnt[kLdsBins];  // counts, then the workgroup's first slot
     const int32_t nb = ctl->cur_nb, ne = ctl->cur_ne;
-    const int64_t p = (int64_t)blockIdx.x * kT + threadIdx.x;
-    const int32_t node = p < n ? pn_src[p] : -1;
-    const bool act = node >= nb && node < ne;
-    int64_t hbin = 0, c = 0, nbeg = 0, nct = 0;
-    double4 q = make_double4(0.0, 0.0, 0.0, 0.0);
-    if (act) {
-        const Node N = nodes[node];
-        const int64_t i = node - nb;
-        const int b = bsel[i];
-        q = Psrc[p];
-        const int cx = subcell(q.x, N.lo[0], N.hi[0], b);
-        const int cy = subcell(q.y, N.lo[1], N.hi[1], b);
-        const int cz = subcell(q.z, N.lo[2], N.hi[2], b);
-        c = cx + (int64_t)b * (cy + (int64_t)b * cz);
-        hbin = selofs[i] + c;
-        nbeg = N.beg;
-        nct = N.ctab;
+    const int64_t base = (int64_t)blockIdx.x * kRunR;
+    const int32_t home = home_cell(pn_src, base, n, nb, ne);
+    int64_t wlo = 0;
+    int32_t wlen = 0;
+    if (home >= 0) {
+        const int b = bsel[home - nb];
+        if ((int64_t)b * b * b <= kLdsBins) {
+            wlo = selofs[home - nb];
+            wlen = b * b * b;
+        }
     }
-    const int32_t slot = wave_agg_slot(cursor, hbin, act);
-    if (!act) return;
-    const int64_t dest = nbeg + cstart[hbin] + slot;
-    Pdst[dest] = q;
-    const int32_t code = ctab[nct + c];
-    pn_dst[dest] = (code & kLeafBit) ? -1 : code;
+    for (int i = threadIdx.x; i < wlen; i += kT) s_cnt[i] = 0;
+    __syncthreads();
+    // Home particles wait in registers for their sub-cell's slots.
+    double4 q[kRunPer];
+    int64_t dst[kRunPer];  // start of the sub-cell's segment; -1: nothing pending
+    int32_t code[kRunPer], bin[kRunPer], rank[kRunPer];
+#pragma unroll
+    for (int j = 0; j < kRunPer; ++j) {
+        const int64_t p = base + j * kT + threadIdx.x;
+        const int32_t node = p < n ? pn_src[p] : -1;
+        const bool act = node >= nb && node < ne;
+        int64_t key = 0, start = 0;
+        int32_t c = 0, cd = -1;
+        double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+        if (act) {
+            const Node& N = nodes[node];
+            const int64_t i = node - nb;
+            const int b = bsel[i];
+            v = Psrc[p];
+            const int cx = subcell(v.x, N.lo[0], N.hi[0], b);
+            const int cy = subcell(v.y, N.lo[1], N.hi[1], b);
+            const int cz = subcell(v.z, N.lo[2], N.hi[2], b);
+            c = cx + b * (cy + b * cz);
+            key = selofs[i] + c;
+            start = (int64_t)N.beg + cstart[key];
+            cd = ctab[N.ctab + c];
+        }
+        const bool local = act && wlen > 0 && node == home;
+        dst[j] = -1;
+        q[j] = v;
+        code[j] = (cd & kLeafBit) ? -1 : cd;
+        bin[j] = c;
+        rank[j] = lds_rank(s_cnt, c, local);
+        if (local) dst[j] = start;
+        const int32_t slot = wave_agg_slot(cursor, key, act && !local);
+        if (act && !local) {
+            const int64_t d = start + slot;
+            Pdst[d] = v;
+            pn_dst[d] = code[j];
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < wlen; i += kT) {
+        const int32_t v = s_cnt[i];
+        if (v) s_cnt[i] = atomicAdd(&cursor[wlo + i], v);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < kRunPer; ++j) {
+        if (dst[j] < 0) continue;
+        const int64_t d = dst[j] + s_cnt[bin[j]] + rank[j];
+        if ((uint64_t)d >= (uint64_t)n) continue;  // cannot happen; keeps a slot error off memory
+        Pdst[d] = q[j];
+        pn_dst[d] = code[j];
+    }
 }
 
 // The next level becomes the current one.
@@ -602,29 +739,107 @@ __device__ __forceinline__ uint64_t grid21(double x, double lo, double scale) {
     return v >= 2097151.0 ? 2097151ull : (uint64_t)v;
 }
 
-// Leaves of at most one work item (kGroup particles): the order inside a
-// work item is free, so such a leaf keeps the order of the Morton pre-sort.
-// One wavefront per leaf copies it into the tree-ordered array and records
-// its smallest and largest original index.
-__global__ __launch_bounds__(kT) void k_leaf_small(const Leaf* __restrict__ leaves,
-                                                   const int32_t* __restrict__ ldepth,
-                                                   const Ctl* __restrict__ ctl,
-                                                   const double4* __restrict__ P0,
-                                                   const double4* __restrict__ P1,
-                                                   double4* __restrict__ pos,
-                                                   int2* __restrict__ lrange) {
+// 63-bit Morton key of a particle on its set's root box (21-bit grid per
+// axis; any monotone map will do: the key only orders particles inside a
+// leaf, so that consecutive particles, hence work items, are compact).
+__device__ __forceinline__ uint64_t leaf_key(const double4& q, const SetDev& S, double sx,
+                                             double sy, double sz) {
+    return spread3_64(grid21(q.x, S.box[0], sx)) | (spread3_64(grid21(q.y, S.box[1], sy)) << 1) |
+           (spread3_64(grid21(q.z, S.box[2], sz)) << 2);
+}
+
+constexpr int kWaveSort = 512;  // leaves up to this size are sorted by one wavefront
+
+// Leaves of at most kWaveSort particles, one wavefront per leaf, into the
+// tree-ordered array with their smallest and largest original index.  A
+// leaf of at most one work item (kGroup particles) keeps the order it has:
+// the order inside a work item is free.  A larger one is put in Morton order
+// on a 128^3 grid over the leaf's own bounding box, so that its work items
+// (consecutive runs of kGroup) are compact.  The sort key is one 32-bit word,
+// the 21-bit grid code above the particle's 9-bit position in the leaf
+// (unique keys, and the position comes back out of the key), sorted by a
+// bitonic network in the wavefront's slice of shared memory, which needs no
+// workgroup barrier.
+__global__ __launch_bounds__(kT) void k_leaf_wave(const Leaf* __restrict__ leaves,
+                                                  const int32_t* __restrict__ ldepth,
+                                                  const Ctl* __restrict__ ctl,
+                                                  const double4* __restrict__ P0,
+                                                  const double4* __restrict__ P1,
+                                                  double4* __restrict__ pos,
+                                                  int2* __restrict__ lrange) {
+    static_assert(kWaveSort <= 512, "the position in the leaf takes 9 bits of the key");
+    __shared__ uint32_t s_key[kT / 64][kWaveSort];
+    uint32_t* const key = s_key[threadIdx.x >> 6];
     const int64_t nl = ctl->n_leaves;
     const int lane = lane_id();
     const int64_t nw = ((int64_t)gridDim.x * kT) >> 6;
     for (int64_t li = ((int64_t)blockIdx.x * kT + threadIdx.x) >> 6; li < nl; li += nw) {
         const Leaf L = leaves[li];
-        if (L.cnt > kGroup) continue;  // uniform over the wavefront
+        if (L.cnt > kWaveSort) continue;  // uniform over the wavefront; k_leaf_final
         const double4* src = (ldepth[li] & 1) ? P1 : P0;
         int mn = 0x7fffffff, mx = -1;
-        if (lane < L.cnt) {
-            const double4 q = src[L.beg + lane];
-            pos[L.beg + lane] = q;
-            mn = mx = (int)q.w;
+        if (L.cnt <= kGroup) {
+            if (lane < L.cnt) {
+                const double4 q = src[L.beg + lane];
+                pos[L.beg + lane] = q;
+                mn = mx = (int)q.w;
+            }
+        } else {
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int k = lane; k < L.cnt; k += 64) {
+                const double4 q = src[L.beg + k];
+                lo[0] = fmin(lo[0], q.x);
+                hi[0] = fmax(hi[0], q.x);
+                lo[1] = fmin(lo[1], q.y);
+                hi[1] = fmax(hi[1], q.y);
+                lo[2] = fmin(lo[2], q.z);
+                hi[2] = fmax(hi[2], q.z);
+                mn = min(mn, (int)q.w);
+                mx = max(mx, (int)q.w);
+            }
+            double sc[3];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                lo[d] = wave_min(lo[d]);
+                hi[d] = wave_max(hi[d]);
+                sc[d] = 128.0 / fmax(hi[d] - lo[d], 1e-300);
+            }
+            int P = 2 * kGroup;
+            while (P < L.cnt) P <<= 1;
+            for (int k = lane; k < P; k += 64) {
+                uint32_t kv = 0xffffffffu;
+                if (k < L.cnt) {
+                    const double4 q = src[L.beg + k];
+                    const double g[3] = {q.x, q.y, q.z};
+                    uint32_t c[3];
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        const double v = (g[d] - lo[d]) * sc[d];
+                        c[d] = v >= 127.0 ? 127u : (v >= 0.0 ? (uint32_t)v : 0u);
+                    }
+                    kv = ((spread3(c[0]) | (spread3(c[1]) << 1) | (spread3(c[2]) << 2)) << 9) |
+                         (uint32_t)k;
+                }
+                key[k] = kv;
+            }
+            wave_lds_sync();
+            for (int kk = 2; kk <= P; kk <<= 1) {
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    // Pair t: a has bit j clear, c = a + j.
+                    for (int t = lane; t < P / 2; t += 64) {
+                        const int a = ((t & ~(j - 1)) << 1) | (t & (j - 1));
+                        const int c = a | j;
+                        const uint32_t ka = key[a], kc = key[c];
+                        const uint32_t small = min(ka, kc), large = max(ka, kc);
+                        const bool up = (a & kk) == 0;
+                        key[a] = up ? small : large;
+                        key[c] = up ? large : small;
+                    }
+                    wave_lds_sync();
+                }
+            }
+            for (int k = lane; k < L.cnt; k += 64) pos[L.beg + k] = src[L.beg + (key[k] & 511u)];
+            wave_lds_sync();  // the next leaf reuses the slice
         }
 #pragma unroll
         for (int d = 32; d > 0; d >>= 1) {
@@ -635,8 +850,9 @@ __global__ __launch_bounds__(kT) void k_leaf_small(const Leaf* __restrict__ leav
     }
 }
 
-// Final pass: each leaf, Morton-sorted on its set's root box (ties by
-// original index), into the tree-ordered particle array, with the leaf's
+// Leaves above kWaveSort particles (a cell at the depth guard, or a large
+// s), one workgroup per leaf: Morton-sorted on the set's root box (ties by
+// original index) into the tree-ordered particle array, with the leaf's
 // smallest and largest original index.
 __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leaves,
                                                    const int32_t* __restrict__ ldepth,
@@ -653,7 +869,7 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
     const int64_t nl = ctl->n_leaves;
     for (int64_t li = blockIdx.x; li < nl; li += gridDim.x) {
         const Leaf L = leaves[li];
-        if (L.cnt <= kGroup) continue;  // done by k_leaf_small
+        if (L.cnt <= kWaveSort) continue;  // done by k_leaf_wave
         const double4* src = (ldepth[li] & 1) ? P1 : P0;
         const SetDev& S = sets[set_of(sets, nsets, L.beg)];
         {
@@ -681,8 +897,6 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
             __syncthreads();
             continue;
         }
-        // 21-bit grid coordinates on the set's root box (any monotone map
-        // will do: the key only orders particles inside a leaf).
         const double sx = (double)(1 << 21) / fmax(S.box[3] - S.box[0], 1e-300);
         const double sy = (double)(1 << 21) / fmax(S.box[4] - S.box[1], 1e-300);
         const double sz = (double)(1 << 21) / fmax(S.box[5] - S.box[2], 1e-300);
@@ -691,10 +905,7 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
         for (int k = threadIdx.x; k < P; k += kT) {
             if (k < L.cnt) {
                 const double4 q = src[L.beg + k];
-                const uint64_t kx = grid21(q.x, S.box[0], sx);
-                const uint64_t ky = grid21(q.y, S.box[1], sy);
-                const uint64_t kz = grid21(q.z, S.box[2], sz);
-                key[k] = spread3_64(kx) | (spread3_64(ky) << 1) | (spread3_64(kz) << 2);
+                key[k] = leaf_key(q, S, sx, sy, sz);
                 val[k] = (int32_t)q.w;
             } else {
                 key[k] = ~0ull;
@@ -922,6 +1133,7 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
     DBuf* Ps[2] = {&W.P0, &W.P1};
     DBuf* Ns[2] = {&W.pn0, &W.pn1};
     const unsigned gN = grid_for(std::max<int64_t>(n, 1), kT);
+    const unsigned gR = grid_for(std::max<int64_t>(n, 1), kRunR);
     const int64_t nc = t.node_cap;
     int level = 0;
     for (; level < levels; ++level) {
@@ -936,9 +1148,9 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
         hipLaunchKernelGGL(k_zero2_dev, dim3(kPersistBlocks), dim3(256), 0, st, W.hist.as<int32_t>(),
                            W.cursor.as<int32_t>(), &ctl->hist_len);
         BT_LAUNCH();
-        hipLaunchKernelGGL(k_histogram, dim3(gN), dim3(kT), 0, st, Ps[par]->as<double4>(),
-                           Ns[par]->as<int32_t>(), n, t.nodes.as<Node>(), t.sets.as<SetDev>(), ctl,
-                           W.hoff.as<int64_t>(), W.hist.as<int32_t>());
+        hipLaunchKernelGGL(k_histogram, dim3(gR), dim3(kT), 0, st, Ps[par]->as<double4>(),
+                           Ns[par]->as<int32_t>(), n, t.nodes.as<Node>(), ctl, W.hoff.as<int64_t>(),
+                           W.hist.as<int32_t>());
         BT_LAUNCH();
         hipLaunchKernelGGL(k_select, dim3(kPersistBlocks), dim3(kT), 0, st, t.nodes.as<Node>(),
                            t.sets.as<SetDev>(), ctl, W.hoff.as<int64_t>(), W.hist.as<int32_t>(),
@@ -962,7 +1174,7 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
                            W.ibase.as<int64_t>(), W.lbase.as<int64_t>(), W.ctoff.as<int64_t>(),
                            t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.ldepth.as<int32_t>());
         BT_LAUNCH();
-        hipLaunchKernelGGL(k_scatter, dim3(gN), dim3(kT), 0, st, Ps[par]->as<double4>(),
+        hipLaunchKernelGGL(k_scatter, dim3(gR), dim3(kT), 0, st, Ps[par]->as<double4>(),
                            Ps[par ^ 1]->as<double4>(), Ns[par]->as<int32_t>(),
                            Ns[par ^ 1]->as<int32_t>(), n, t.nodes.as<Node>(), ctl,
                            W.bsel.as<int32_t>(), W.selofs.as<int64_t>(), W.cstart.as<int32_t>(),
@@ -1001,7 +1213,7 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
     std::swap(t.ldepth.p, t.ldepth2.p);
     std::swap(t.ldepth.bytes, t.ldepth2.bytes);
 
-    hipLaunchKernelGGL(k_leaf_small, dim3(kPersistBlocks), dim3(kT), 0, st, t.leaves.as<Leaf>(),
+    hipLaunchKernelGGL(k_leaf_wave, dim3(kPersistBlocks), dim3(kT), 0, st, t.leaves.as<Leaf>(),
                        t.ldepth.as<int32_t>(), ctl, W.P0.as<double4>(), W.P1.as<double4>(),
                        t.pos.as<double4>(), t.lrange.as<int2>());
     BT_LAUNCH();

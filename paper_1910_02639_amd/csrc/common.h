@@ -333,6 +333,23 @@ __host__ __device__ inline int subcell(double x, double lo, double hi, int b) {
     return (int)v;
 }
 
+// subcell() in two steps, for several b on one cell: the fraction
+// t = (x - lo) / w does not depend on b (0 for a zero extent, which then
+// maps to sub-cell 0 as above), and subcell_of(t, b) equals
+// subcell(x, lo, hi, b) bit for bit.
+__host__ __device__ inline double subcell_frac(double x, double lo, double hi) {
+    double w = hi - lo;
+    if (!(w > 0.0)) return 0.0;
+    return (x - lo) / w;
+}
+
+__host__ __device__ inline int subcell_of(double t, int b) {
+    double v = floor(t * (double)b);
+    if (!(v >= 0.0)) return 0;
+    if (v > (double)(b - 1)) return b - 1;
+    return (int)v;
+}
+
 // Box of sub-cell c along one axis: lo + (w*c)/b .. lo + (w*(c+1))/b.
 __host__ __device__ inline double cell_edge(double lo, double hi, int c, int b) {
     double w = hi - lo;

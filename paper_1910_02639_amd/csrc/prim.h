@@ -53,6 +53,13 @@ __device__ __forceinline__ int32_t wave_agg_slot(int32_t* counter, int64_t idx, 
     return base + rank;
 }
 
+// Orders a wavefront's shared-memory accesses: what its lanes stored before
+// the call is what its lanes load after it.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <class T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
     const int l = lane_id();
