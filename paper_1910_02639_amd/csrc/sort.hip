@@ -6,8 +6,9 @@
 //
 // Per pass: (1) per-tile digit histograms in LDS, written digit-major;
 // (2) exclusive scan of the digit-major counts; (3) each tile ranks its keys
-// stably (striped order; within a wavefront, lanes with equal digits are
-// found with 8 ballots) and scatters them.
+// stably (within a wavefront, lanes with equal digits are found with 8
+// ballots), reorders them by digit in LDS and writes each digit's run to
+// consecutive addresses.
 #include "prim.h"
 
 namespace bt {
@@ -42,20 +43,32 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
                                                       int shift,
                                                       const int64_t* __restrict__ off,
                                                       int64_t ntiles) {
-    __shared__ int64_t run[kDigits];
+    __shared__ uint32_t sk[kTile];
+    __shared__ int32_t sv[kTile];
+    __shared__ int32_t cnt[kDigits];  // keys of each digit ranked so far, then digit starts
     __shared__ int32_t wc[kW][kDigits];
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    run[t] = off[(int64_t)t * ntiles + blockIdx.x];
+    __shared__ int64_t scan_tmp[kW + 1];
+    const int t = threadIdx.x, w = t >> 6;
+    cnt[t] = 0;
     for (int k = 0; k < kW; ++k) wc[k][t] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kTile;
+    // Rank every key of the tile among the tile's keys of its digit, in
+    // index order (stable): earlier rounds, then lower wavefronts, then
+    // lower lanes.
+    uint32_t key[kRounds];
+    int32_t val[kRounds], rank[kRounds];
+#pragma unroll
     for (int r = 0; r < kRounds; ++r) {
         const int64_t i = base + r * kT + t;
         const bool v = i < n;
-        const uint32_t key = v ? kin[i] : 0u;
-        const int32_t val = v ? vin[i] : 0;
-        const uint32_t d = (key >> shift) & 0xffu;
-        // lanes of this wavefront holding the same digit
+        key[r] = v ? kin[i] : 0xffffffffu;
+        val[r] = v ? vin[i] : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        const bool v = base + r * kT + t < n;
+        const uint32_t d = (key[r] >> shift) & 0xffu;
         uint64_t peers = __ballot(v);
 #pragma unroll
         for (int b = 0; b < 8; ++b) {
@@ -63,19 +76,38 @@ __global__ __launch_bounds__(kT) void k_radix_scatter(const uint32_t* __restrict
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const int below = lanes_below(peers);
-        const bool leader = v && below == 0;
-        if (leader) wc[w][d] = __popcll(peers);
+        if (v && below == 0) wc[w][d] = __popcll(peers);
         __syncthreads();
-        if (v) {
-            int64_t pos = run[d] + below;
-            for (int k = 0; k < w; ++k) pos += wc[k][d];
-            kout[pos] = key;
-            vout[pos] = val;
-        }
+        int rk = cnt[d] + below;
+        for (int k = 0; k < w; ++k) rk += wc[k][d];
+        rank[r] = v ? rk : -1;
         __syncthreads();
-        run[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
+        cnt[t] += wc[0][t] + wc[1][t] + wc[2][t] + wc[3][t];
         for (int k = 0; k < kW; ++k) wc[k][t] = 0;
         __syncthreads();
+    }
+    // Digit starts inside the tile; keys move to their place in LDS.
+    int64_t tot;
+    const int32_t start = (int32_t)block_excl_scan<kT>(cnt[t], scan_tmp, &tot);
+    cnt[t] = start;
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < kRounds; ++r) {
+        if (rank[r] < 0) continue;
+        const int p = cnt[(key[r] >> shift) & 0xffu] + rank[r];
+        sk[p] = key[r];
+        sv[p] = val[r];
+    }
+    __syncthreads();
+    // Out in tile order: keys of one digit are consecutive here and land on
+    // consecutive addresses of their digit's output range.
+    const int m = (int)min<int64_t>(kTile, n - base);
+    for (int p = t; p < m; p += kT) {
+        const uint32_t k = sk[p];
+        const uint32_t d = (k >> shift) & 0xffu;
+        const int64_t g = off[(int64_t)d * ntiles + blockIdx.x] + (p - cnt[d]);
+        kout[g] = k;
+        vout[g] = sv[p];
     }
 }
 
