@@ -177,11 +177,27 @@ __global__ __launch_bounds__(kT) void k_gather(const double4* __restrict__ orig,
     const Tile T = tiles[blockIdx.x];
     const int32_t root = sets[T.set].root;
     const int32_t pn = (root != kEmpty && !(root & kLeafBit)) ? root : -1;
-    for (int64_t k = T.beg + threadIdx.x; k < T.end; k += kT) {
-        const int32_t i = perm[k];
-        const double4 q = orig[i];
-        P0[k] = make_double4(q.x, q.y, q.z, (double)i);
-        pnode[k] = pn;
+    // Eight particles per thread and step, so that eight independent
+    // index -> particle load chains are in flight.
+    constexpr int kU = 8;
+    for (int64_t k0 = T.beg + threadIdx.x; k0 < T.end; k0 += kT * kU) {
+        int32_t i[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            const int64_t k = k0 + u * kT;
+            i[u] = k < T.end ? perm[k] : -1;
+        }
+        double4 q[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u)
+            if (i[u] >= 0) q[u] = orig[i[u]];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+            if (i[u] < 0) continue;
+            const int64_t k = k0 + u * kT;
+            P0[k] = make_double4(q[u].x, q[u].y, q[u].z, (double)i[u]);
+            pnode[k] = pn;
+        }
     }
 }
 

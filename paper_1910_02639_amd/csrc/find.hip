@@ -295,6 +295,7 @@ __global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
                                              const int2* __restrict__ lrange,
                                              const SetDev* __restrict__ sets,
                                              const double* __restrict__ h,
+                                             double* __restrict__ hs,
                                              int4* __restrict__ whdr, int2* __restrict__ wl,
                                              int64_t wl_cap, unsigned long long* __restrict__ wcur,
                                              Ctl* __restrict__ ctl) {
@@ -310,7 +311,14 @@ __global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
     const int lane = threadIdx.x;
     const bool qv = lane < ch.cnt;
     const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
-    const double R = qv ? 2.0 * h[ch.beg + lane] : 0.0;
+    // h of the item's particles, also kept in tree order for the later
+    // search kernels (the work items cover every particle once).
+    double hv = 0.0;
+    if (qv) {
+        hv = h[(int)qp.w];
+        hs[ch.beg + lane] = hv;
+    }
+    const double R = 2.0 * hv;
     double elo[3], ehi[3];
     item_box(qv, qp, R, elo, ehi);
     const int32_t root_code = __builtin_amdgcn_readfirstlane(sets[ch.set].root);
@@ -1228,14 +1236,6 @@ __global__ void k_check_h(const double* __restrict__ h, int64_t n, Ctl* __restri
     if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->data_bad, 2);
 }
 
-// Smoothing lengths in tree order: hs[p] = h of the particle at position p,
-// so that a work item reads its queries' h without waiting for their index.
-__global__ void k_gather_h(const double* __restrict__ h, const double4* __restrict__ pos,
-                           int64_t n, double* __restrict__ hs) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) hs[p] = h[(int)pos[p].w];
-}
-
 // Lists per set: totals[k] = offsets[end of set k] - offsets[start of set k].
 __global__ void k_set_totals(const int64_t* __restrict__ offsets, const SetDev* __restrict__ sets,
                              int nsets, int64_t* __restrict__ totals) {
@@ -1314,16 +1314,14 @@ void find_begin(Tree& t, const double* h, hipStream_t st) {
     hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
                        st, h, t.n, t.ctl.as<Ctl>());
     BT_LAUNCH();
-    hipLaunchKernelGGL(k_gather_h, dim3(grid_for(t.n, 256)), dim3(256), 0, st, h,
-                       t.pos.as<double4>(), t.n, t.hs.as<double>());
-    BT_LAUNCH();
 }
 
 void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st) {
     const unsigned g = (unsigned)std::max<int64_t>(1, grid);
     hipLaunchKernelGGL(k_walk, dim3(g), dim3(64), 0, st, t.chunks.as<Chunk>(), t.pos.as<double4>(),
                        t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
-                       t.lrange.as<int2>(), t.sets.as<SetDev>(), t.hs.as<double>(), t.whdr.as<int4>(),
+                       t.lrange.as<int2>(), t.sets.as<SetDev>(), h, t.hs.as<double>(),
+                       t.whdr.as<int4>(),
                        t.wl.as<int2>(), t.wl_cap,
                        t.stripes.as<unsigned long long>() + kStripes * kStripeStride, t.ctl.as<Ctl>());
     BT_LAUNCH();
