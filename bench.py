@@ -150,6 +150,7 @@ def bench_single(name, precision, steps, warmup, compare, tuner, bucket=0):
            "neighbours_total": total, "pair_tests_per_particle": st["pair_tests"] / n,
            "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, st["pair_tests"]),
            "exhaustive_items": st["brute_chunks"],
+           "exhaustive_units": st["brute_units"], "split_items": st["split_items"],
            "tree": {"depth": st["depth"], "internal": st["n_internal"],
                     "leaves": st["n_leaves"], "b_hist": st["b_hist"]},
            "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], ops,
@@ -259,6 +260,7 @@ def bench_batch(a, tuner):
         "pair_tests_per_particle": st["pair_tests"] / n,
         "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, st["pair_tests"]),
         "exhaustive_items": st["brute_chunks"],
+        "exhaustive_units": st["brute_units"], "split_items": st["split_items"],
         "graph": {"launches": st["graph_launches"], "recordings": st["graph_captures"]},
         "tree": {"depth": st["depth"], "internal": st["n_internal"], "leaves": st["n_leaves"]},
         "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], OPS_PER_TEST_F32,

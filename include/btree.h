@@ -98,6 +98,9 @@ typedef struct {
     int64_t split_items;    /* work items whose candidates overflowed shared
                                memory and were searched again in groups of 8
                                queries, then singly                            */
+    int64_t brute_units;    /* units (1 to 64 queries of one set) that took
+                               the exhaustive path; brute_chunks counts their
+                               queries                                          */
 } btree_stats_t;
 
 typedef struct btree_tree* btree_handle;

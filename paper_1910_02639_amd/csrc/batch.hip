@@ -350,6 +350,7 @@ btree_status btree_batch_stats(btree_batch_handle H, btree_stats_t* out) {
     out->brute_chunks = (int64_t)t.host_stats.brute;
     out->candidates = (int64_t)t.host_stats.candidates;
     out->split_items = (int64_t)t.host_stats.split;
+    out->brute_units = (int64_t)t.host_ctl.nbunits;
     for (int k = 0; k < kPhases; ++k) {
         out->phase_ms[k] = t.timer.sum_ms[k];
         out->phase_calls[k] = t.timer.calls[k];

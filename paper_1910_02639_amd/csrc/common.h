@@ -190,6 +190,7 @@ struct Ctl {
     uint32_t queue;             // next search work item (atomic)
     uint32_t nbrute;            // work items on the exhaustive path (atomic)
     uint32_t nsplit2, nsplit3;  // units left for the second and third split levels (atomic)
+    uint32_t nbunits;           // exhaustive-path units after regrouping by set
 };
 
 // Allocation from the search's pools (row scratch, walk lists) goes through
@@ -276,7 +277,9 @@ struct Tree {
     DBuf stats;    // Stats
     DBuf split;    // three lists of Chunk (leaf_cap each): units of the split levels
     DBuf split_ci; // int32 per entry of the first list: the work item it came from
-    DBuf blist;    // Chunk per query taken by the exhaustive path
+    DBuf blist;    // Chunk per unit (1 to 64 queries of one set) listed for the exhaustive path
+    DBuf bq;       // tree positions of the exhaustive path's queries, grouped by set
+    DBuf bset;     // per set: listed queries, fill cursor, query offsets, unit offsets
     DBuf scan_tmp; // scan block sums
     DBuf scratch;  // int32 rows of the search, in work-item order
     DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)

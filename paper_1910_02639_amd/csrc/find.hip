@@ -958,10 +958,12 @@ constexpr int kLMaxSplit = 2048;
 // Lists a unit (up to 64 queries of one set) for the exhaustive path.
 __device__ __forceinline__ void to_brute(const Chunk q, const double4* __restrict__ pos,
                                          int64_t* __restrict__ soff, Ctl* __restrict__ ctl,
-                                         Chunk* __restrict__ brute, Stats* __restrict__ stats) {
+                                         Chunk* __restrict__ brute, int32_t* __restrict__ bcnt,
+                                         Stats* __restrict__ stats) {
     if (threadIdx.x < q.cnt) soff[(int)pos[q.beg + threadIdx.x].w] = -1;
     if (threadIdx.x == 0) {
         brute[atomicAdd(&ctl->nbrute, 1u)] = Chunk{q.beg, q.cnt, q.set, 0};
+        atomicAdd(&bcnt[q.set], q.cnt);
         atomicAdd(&stats->brute, (unsigned long long)q.cnt);
     }
 }
@@ -1001,6 +1003,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
                                                      unsigned long long* __restrict__ scur,
                                                      Ctl* __restrict__ ctl,
                                                      Chunk* __restrict__ brute,
+                                                     int32_t* __restrict__ bcnt,
                                                      Stats* __restrict__ stats) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     // Units of this level: level 1 takes each listed item whole; levels 2
@@ -1017,7 +1020,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         const int64_t nset = sets[unit.set].n;
         __syncthreads();  // the previous unit is done with the shared memory
         if (LEVEL == 1 && nset <= kDenseSet && src.pad != kNoCount && 4 * (int64_t)src.pad > nset) {
-            to_brute(unit, pos, soff, ctl, brute, stats);
+            to_brute(unit, pos, soff, ctl, brute, bcnt, stats);
             continue;
         }
         // Level 1 takes the item whole: its walk list, if whole, still holds.
@@ -1028,7 +1031,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         if (!C) continue;
         __syncthreads();
         if (LEVEL == 3 || (nset <= kDenseSet && C != kNoCount && 4 * (int64_t)C > nset)) {
-            to_brute(unit, pos, soff, ctl, brute, stats);
+            to_brute(unit, pos, soff, ctl, brute, bcnt, stats);
         } else if (threadIdx.x == 0) {
             uint32_t* cnt = LEVEL == 1 ? &ctl->nsplit2 : &ctl->nsplit3;
             next[atomicAdd(cnt, 1u)] = Chunk{unit.beg, unit.cnt, unit.set, C};
@@ -1099,18 +1102,76 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
     }
 }
 
-// Exhaustive path for the listed units (up to 64 queries of one set, lane q
-// of every wavefront holds query q): the set's particles, already in
-// original index order in `orig`, pass through shared memory in tiles of
-// kDenseTile; wavefront w tests its quarter of each tile with the FP64
-// predicate, one bit per (query, candidate).  Count mode sums the bits;
-// fill mode writes each row in ascending index at offsets[i] plus the hits
-// of the earlier tiles and of the lower wavefronts.  Persistent over the list.
+// The exhaustive path takes its queries in units of up to 64 queries of one
+// set.  The split levels list units of 1, 8 or 64 queries; before the
+// sweep they are regrouped by set into full units, so that every lane of
+// the sweep has a query.  `bset` holds, for nsets sets: listed queries
+// [0, nsets), fill cursors [nsets, 2 nsets), query offsets
+// [2 nsets, 3 nsets + 1) and unit offsets [3 nsets + 1, 4 nsets + 2).
+
+// Query and unit offsets per set (one workgroup).
+__global__ __launch_bounds__(kWG) void k_brute_plan(int32_t* __restrict__ bset, int nsets,
+                                                    Ctl* __restrict__ ctl) {
+    __shared__ int64_t sh[kWaves + 1];
+    const int32_t* cnt = bset;
+    int32_t* fill = bset + nsets;
+    int32_t* off = bset + 2 * nsets;
+    int32_t* uoff = off + nsets + 1;
+    int64_t qrun = 0, urun = 0;
+    for (int s0 = 0; s0 < nsets; s0 += kWG) {
+        const int s = s0 + (int)threadIdx.x;
+        const int64_t c = s < nsets ? cnt[s] : 0;
+        int64_t tq, tu;
+        const int64_t eq = block_excl_scan<kWG>(c, sh, &tq);
+        const int64_t eu = block_excl_scan<kWG>((c + kGroup - 1) / kGroup, sh, &tu);
+        if (s < nsets) {
+            off[s] = (int32_t)(qrun + eq);
+            uoff[s] = (int32_t)(urun + eu);
+            fill[s] = 0;
+        }
+        qrun += tq;
+        urun += tu;
+    }
+    if (threadIdx.x == 0) {
+        off[nsets] = (int32_t)qrun;
+        uoff[nsets] = (int32_t)urun;
+        ctl->nbunits = (uint32_t)urun;
+    }
+}
+
+// The listed units' queries into their set's segment of `bq` (one
+// wavefront per listed unit; the order inside a set is free).
+__global__ __launch_bounds__(kWG) void k_brute_group(const Chunk* __restrict__ blist,
+                                                     const Ctl* __restrict__ ctl,
+                                                     int32_t* __restrict__ bset, int nsets,
+                                                     int32_t* __restrict__ bq) {
+    int32_t* fill = bset + nsets;
+    const int32_t* off = bset + 2 * nsets;
+    const uint32_t nb = ctl->nbrute;
+    const int lane = lane_id();
+    const int64_t nw = ((int64_t)gridDim.x * kWG) >> 6;
+    for (int64_t k = ((int64_t)blockIdx.x * kWG + threadIdx.x) >> 6; k < nb; k += nw) {
+        const Chunk ch = blist[k];
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&fill[ch.set], ch.cnt);
+        base = __shfl(base, 0, 64);
+        if (lane < ch.cnt) bq[off[ch.set] + base + lane] = ch.beg + lane;
+    }
+}
+
+// Exhaustive sweep of the regrouped units (lane q of every wavefront holds
+// query q of the unit): the set's particles, already in original index
+// order in `orig`, pass through shared memory in tiles of kDenseTile;
+// wavefront w tests its quarter of each tile with the FP64 predicate, one
+// bit per (query, candidate).  Count mode sums the bits; fill mode writes
+// each row in ascending index at offsets[i] plus the hits of the earlier
+// tiles and of the lower wavefronts.  Persistent over the units.
 constexpr int kDenseTile = 768;
 constexpr int kDenseWords = kDenseTile / kWaves / 32;  // words per wavefront and tile
 
 template <int MODE>
-__global__ __launch_bounds__(kWG) void k_dense(const Chunk* __restrict__ blist,
+__global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
+                                               const int32_t* __restrict__ bset, int nsets,
                                                const SetDev* __restrict__ sets,
                                                const double4* __restrict__ pos,
                                                const double4* __restrict__ orig,
@@ -1123,16 +1184,29 @@ __global__ __launch_bounds__(kWG) void k_dense(const Chunk* __restrict__ blist,
     __shared__ int32_t s_cnt[kWaves][64];
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     if (MODE == kFill && ((ctl->overflow & kOvfChunks) || offsets[n] > capacity)) return;
-    const uint32_t nb = ctl->nbrute;
+    const uint32_t nu = ctl->nbunits;
+    const int32_t* bcnt = bset;
+    const int32_t* off = bset + 2 * nsets;
+    const int32_t* uoff = off + nsets + 1;
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    for (uint32_t k = blockIdx.x; k < nb; k += gridDim.x) {
-        const Chunk ch = blist[k];
-        const int64_t jb = sets[ch.set].beg, jn = sets[ch.set].n;
-        const bool qv = lane < ch.cnt;
-        const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+    for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
+        // Set of unit u: the last set whose first unit is at most u.
+        int slo = 0, shi = nsets - 1;
+        while (slo < shi) {
+            const int mid = (slo + shi + 1) >> 1;
+            if ((uint32_t)uoff[mid] <= u) slo = mid;
+            else shi = mid - 1;
+        }
+        const int set = slo;
+        const int j = (int)u - uoff[set];
+        const int qcnt = min(kGroup, bcnt[set] - kGroup * j);
+        const int64_t jb = sets[set].beg, jn = sets[set].n;
+        const bool qv = lane < qcnt;
+        const int qpos = qv ? bq[off[set] + kGroup * j + lane] : 0;
+        const double4 qp = qv ? pos[qpos] : make_double4(0.0, 0.0, 0.0, 0.0);
         const int qidx = (int)qp.w;
-        const double R = qv ? 2.0 * h[ch.beg + lane] : 0.0;
+        const double R = qv ? 2.0 * h[qpos] : 0.0;
         const double r2 = qv ? __dmul_rn(R, R) : -1.0;  // nothing is below -1
         int64_t run = (MODE == kFill && qv) ? offsets[qidx] : 0;
         int64_t hits = 0;
@@ -1208,14 +1282,17 @@ __global__ __launch_bounds__(kWG) void k_dense(const Chunk* __restrict__ blist,
 
 // Clears the search's part of the control block and the search counters.
 __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
-                             unsigned long long* __restrict__ stripes) {
+                             unsigned long long* __restrict__ stripes, int32_t* __restrict__ bcnt,
+                             int nsets) {
     if (threadIdx.x < 2 * kStripes) stripes[threadIdx.x * kStripeStride] = 0;
+    for (int s = threadIdx.x; s < nsets; s += blockDim.x) bcnt[s] = 0;
     if (threadIdx.x == 0) {
         ctl->queue = 0;
         ctl->nsplit = 0;
         ctl->nsplit2 = 0;
         ctl->nsplit3 = 0;
         ctl->nbrute = 0;
+        ctl->nbunits = 0;
         ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
         ctl->overflow &= ~(kOvfScratch | kOvfCapacity | kOvfChunks | kOvfWalk);
         stats->pair_tests = 0;
@@ -1268,7 +1345,8 @@ void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* 
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
-                       t.ctl.as<Ctl>(), t.blist.as<Chunk>(), t.stats.as<Stats>());
+                       t.ctl.as<Ctl>(), t.blist.as<Chunk>(), t.bset.as<int32_t>(),
+                       t.stats.as<Stats>());
     BT_LAUNCH();
 }
 
@@ -1309,7 +1387,8 @@ void find_reserve(Tree& t, int64_t entries) {
 
 void find_begin(Tree& t, const double* h, hipStream_t st) {
     hipLaunchKernelGGL(k_find_reset, dim3(1), dim3(2 * kStripes), 0, st, t.ctl.as<Ctl>(),
-                       t.stats.as<Stats>(), t.stripes.as<unsigned long long>());
+                       t.stats.as<Stats>(), t.stripes.as<unsigned long long>(),
+                       t.bset.as<int32_t>(), (int)t.nsets);
     BT_LAUNCH();
     hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
                        st, h, t.n, t.ctl.as<Ctl>());
@@ -1336,8 +1415,15 @@ void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStre
 void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
     if (t.prm.precision == BTREE_FP32_FILTER) launch_split<true>(t, h, counts, st);
     else launch_split<false>(t, h, counts, st);
+    hipLaunchKernelGGL(k_brute_plan, dim3(1), dim3(kWG), 0, st, t.bset.as<int32_t>(),
+                       (int)t.nsets, t.ctl.as<Ctl>());
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_brute_group, dim3(kBruteGrid), dim3(kWG), 0, st, t.blist.as<Chunk>(),
+                       t.ctl.as<Ctl>(), t.bset.as<int32_t>(), (int)t.nsets, t.bq.as<int32_t>());
+    BT_LAUNCH();
     hipLaunchKernelGGL((k_dense<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
-                       t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
+                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets,
+                       t.sets.as<SetDev>(), t.pos.as<double4>(),
                        t.orig.as<double4>(), t.hs.as<double>(), counts, nullptr, t.n, (int64_t)0, nullptr,
                        t.ctl.as<Ctl>());
     BT_LAUNCH();
@@ -1357,7 +1443,8 @@ void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t*
 void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,
                    int64_t capacity, int64_t* totals, hipStream_t st) {
     hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
-                       t.blist.as<Chunk>(), t.sets.as<SetDev>(), t.pos.as<double4>(),
+                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets,
+                       t.sets.as<SetDev>(), t.pos.as<double4>(),
                        t.orig.as<double4>(), t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs,
                        t.ctl.as<Ctl>());
     BT_LAUNCH();
