@@ -250,7 +250,7 @@ def bench_batch(a, tuner):
         "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": "Batch64", "sets": len(sizes), "n": n,
                    "set_sizes_min_max": [int(min(sizes)), int(max(sizes))],
-                   "form": "captured HIP graph per step: 6 segments back to back, "
+                   "form": "captured HIP graph per step: 5 segments back to back, "
                            "build + both search passes of all sets",
                    "precision": "fp32_filter+fp64_band", "params": "autotuned per set",
                    "buckets_used": sorted({p["bucket_size"] for p in prm32}),

@@ -14,7 +14,7 @@
 
 namespace bt {
 
-enum { kSegBuild = 0, kSegBegin, kSegSweep, kSegCounts, kSegPlace, kSegFill, kSegs };
+enum { kSegBuild = 0, kSegBegin, kSegSweep, kSegCounts, kSegPlace, kSegs };
 
 struct Batch {
     Tree t;
@@ -89,6 +89,7 @@ void capture(Batch& B, const double* x, const double* y, const double* z, const 
              int32_t* counts, int64_t* offsets, int32_t* nbrs, int64_t capacity) {
     Tree& t = B.t;
     B.drop_graph();
+    t.side.ensure();  // the placement segment forks onto it; not created while capturing
     record(B, kSegBuild, [&](hipStream_t s) { build_queue(t, x, y, z, (int)t.level_cap, false, s); });
     record(B, kSegBegin, [&](hipStream_t s) {
         find_begin(t, h, s);
@@ -96,9 +97,8 @@ void capture(Batch& B, const double* x, const double* y, const double* z, const 
     });
     record(B, kSegSweep, [&](hipStream_t s) { find_sweep(t, h, counts, t.chunk_cap, s); });
     record(B, kSegCounts, [&](hipStream_t s) { find_counts_end(t, h, counts, offsets, s); });
-    record(B, kSegPlace, [&](hipStream_t s) { find_place(t, counts, offsets, nbrs, capacity, s); });
-    record(B, kSegFill, [&](hipStream_t s) {
-        find_fill_end(t, h, offsets, nbrs, capacity, t.tot.as<int64_t>(), s);
+    record(B, kSegPlace, [&](hipStream_t s) {
+        find_fill(t, counts, offsets, nbrs, capacity, t.tot.as<int64_t>(), false, s);
     });
     B.recorded = true;
     const void* k[7] = {x, y, z, h, counts, offsets, nbrs};
@@ -124,7 +124,6 @@ void launch(Batch& B, hipStream_t st) {
     T.start(kPhPlace, st);
     BT_HIP(hipGraphLaunch(B.exec[kSegPlace], st));
     T.stop(kPhPlace, st);
-    BT_HIP(hipGraphLaunch(B.exec[kSegFill], st));
     T.stop(kPhPass2, st);
     ++B.launches;
 }

@@ -255,6 +255,25 @@ struct Timer {
     }
 };
 
+// A second stream of the handle, forked from and joined back to the
+// caller's stream with two events, for work that can run beside the main
+// sequence (also inside a graph capture: the fork and join become edges).
+// Created outside any capture.  Default priority.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+    void ensure() {
+        if (!s) BT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        if (!fork) BT_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
+        if (!join) BT_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
+    }
+    ~SideStream() {
+        if (fork) (void)hipEventDestroy(fork);
+        if (join) (void)hipEventDestroy(join);
+        if (s) (void)hipStreamDestroy(s);
+    }
+};
+
 // The handle.
 struct Tree {
     int64_t n = 0;
@@ -289,6 +308,7 @@ struct Tree {
     DBuf wl;       // int2 pool: candidate leaves (first particle, count) of every item
     Work ws;
     Timer timer;
+    SideStream side;
 
     int64_t n_internal = 0, n_leaves = 0, n_chunks = 0, ctab_len = 0;
     int64_t scap = 0;  // scratch capacity, entries
@@ -448,8 +468,8 @@ void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStre
 void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st);
 void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
                 int64_t capacity, hipStream_t st);
-void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,
-                   int64_t capacity, int64_t* totals, hipStream_t st);
+void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
+               int64_t capacity, int64_t* totals, bool time_place, hipStream_t st);
 // Sizes the search scratch for at least `entries` list entries.
 void find_reserve(Tree& t, int64_t entries);
 // Grows the scratch and walk-list pools from the stripe cursors in

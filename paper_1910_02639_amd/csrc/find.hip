@@ -1440,14 +1440,27 @@ void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t*
     BT_LAUNCH();
 }
 
-void find_fill_end(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,
-                   int64_t capacity, int64_t* totals, hipStream_t st) {
-    hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
+// Pass 2: the rows from the scratch into the caller's CSR (k_place, bound by
+// HBM) and, beside it on the handle's side stream, the rows of the
+// exhaustive path (a few workgroups bound by arithmetic); the two write
+// disjoint rows.  Then the per-set totals, when asked for.  `time_place`
+// times k_place alone (not inside a graph capture).
+void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
+               int64_t capacity, int64_t* totals, bool time_place, hipStream_t st) {
+    SideStream& sd = t.side;
+    sd.ensure();
+    BT_HIP(hipEventRecord(sd.fork, st));
+    BT_HIP(hipStreamWaitEvent(sd.s, sd.fork, 0));
+    hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, sd.s,
                        t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets,
-                       t.sets.as<SetDev>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs,
-                       t.ctl.as<Ctl>());
+                       t.sets.as<SetDev>(), t.pos.as<double4>(), t.orig.as<double4>(),
+                       t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs, t.ctl.as<Ctl>());
     BT_LAUNCH();
+    BT_HIP(hipEventRecord(sd.join, sd.s));
+    if (time_place) t.timer.start(kPhPlace, st);
+    find_place(t, counts, offsets, nbrs, capacity, st);
+    if (time_place) t.timer.stop(kPhPlace, st);
+    BT_HIP(hipStreamWaitEvent(st, sd.join, 0));
     if (totals) {
         hipLaunchKernelGGL(k_set_totals, dim3(grid_for(t.nsets, 256)), dim3(256), 0, st, offsets,
                            t.sets.as<SetDev>(), t.nsets, totals);
@@ -1500,10 +1513,8 @@ int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, 
 }
 
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs, hipStream_t st) {
-    t.timer.start(kPhPlace, st);
-    find_place(t, t.p1_counts, offsets, nbrs, INT64_MAX, st);
-    t.timer.stop(kPhPlace, st);
-    find_fill_end(t, h, offsets, nbrs, INT64_MAX, nullptr, st);
+    (void)h;  // pass 1 kept h in tree order
+    find_fill(t, t.p1_counts, offsets, nbrs, INT64_MAX, nullptr, true, st);
 }
 
 }  // namespace bt
