@@ -1101,7 +1101,7 @@ void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off_in, const btree_pa
     t.split_ci.reserve(sizeof(int32_t) * t.leaf_cap);
     t.blist.reserve(sizeof(Chunk) * t.leaf_cap);
     t.bq.reserve(sizeof(int32_t) * nn);
-    t.bset.reserve(sizeof(int32_t) * (4 * (int64_t)nsets + 2));
+    t.bset.reserve(sizeof(int32_t) * (5 * (int64_t)nsets + 3));
     t.ctl.reserve(sizeof(Ctl));
     t.stats.reserve(sizeof(Stats));
     t.tot.reserve(sizeof(int64_t) * (nsets + 1));

@@ -191,6 +191,8 @@ struct Ctl {
     uint32_t nbrute;            // work items on the exhaustive path (atomic)
     uint32_t nsplit2, nsplit3;  // units left for the second and third split levels (atomic)
     uint32_t nbunits;           // exhaustive-path units after regrouping by set
+    uint32_t nbtasks;           // exhaustive count-pass tasks (unit x span of its set)
+    int64_t bspan;              // candidates per exhaustive count-pass task
 };
 
 // Allocation from the search's pools (row scratch, walk lists) goes through
@@ -298,7 +300,7 @@ struct Tree {
     DBuf split_ci; // int32 per entry of the first list: the work item it came from
     DBuf blist;    // Chunk per unit (1 to 64 queries of one set) listed for the exhaustive path
     DBuf bq;       // tree positions of the exhaustive path's queries, grouped by set
-    DBuf bset;     // per set: listed queries, fill cursor, query offsets, unit offsets
+    DBuf bset;     // per set: listed queries, fill cursor, query, unit and count-task offsets
     DBuf scan_tmp; // scan block sums
     DBuf scratch;  // int32 rows of the search, in work-item order
     DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)

@@ -1105,37 +1105,64 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
 // The exhaustive path takes its queries in units of up to 64 queries of one
 // set.  The split levels list units of 1, 8 or 64 queries; before the
 // sweep they are regrouped by set into full units, so that every lane of
-// the sweep has a query.  `bset` holds, for nsets sets: listed queries
-// [0, nsets), fill cursors [nsets, 2 nsets), query offsets
-// [2 nsets, 3 nsets + 1) and unit offsets [3 nsets + 1, 4 nsets + 2).
+// the sweep has a query.  The count pass cuts each unit's sweep over its set
+// into spans of kDenseSpan candidates, one workgroup each, so that a large
+// set does not make one workgroup the critical path; the fill pass (which
+// runs beside the placement) takes each unit whole.  `bset` holds, for
+// nsets sets: listed queries [0, nsets), fill cursors [nsets, 2 nsets),
+// query offsets [2 nsets, 3 nsets + 1), unit offsets [3 nsets + 1,
+// 4 nsets + 2) and count-task offsets [4 nsets + 2, 5 nsets + 3).
+constexpr int kDenseTile = 768;
+constexpr int64_t kDenseSpan = 12 * kDenseTile;
 
-// Query and unit offsets per set (one workgroup).
+__device__ __forceinline__ int64_t dense_spans(int64_t nset, int64_t span) {
+    return nset > 0 ? (nset + span - 1) / span : 1;
+}
+
+// Query, unit and count-task offsets per set (one workgroup).
 __global__ __launch_bounds__(kWG) void k_brute_plan(int32_t* __restrict__ bset, int nsets,
+                                                    const SetDev* __restrict__ sets,
                                                     Ctl* __restrict__ ctl) {
     __shared__ int64_t sh[kWaves + 1];
     const int32_t* cnt = bset;
     int32_t* fill = bset + nsets;
     int32_t* off = bset + 2 * nsets;
     int32_t* uoff = off + nsets + 1;
-    int64_t qrun = 0, urun = 0;
+    int32_t* toff = uoff + nsets + 1;
+    // Span of a count task: kDenseSpan, or the whole set should the tasks
+    // not be countable in 32 bits.
+    int64_t all = 0;
+    for (int s = threadIdx.x; s < nsets; s += kWG)
+        all += (cnt[s] + kGroup - 1) / kGroup * dense_spans(sets[s].n, kDenseSpan);
+    all = block_sum<kWG>(all, sh);
+    const int64_t span = all <= INT32_MAX ? kDenseSpan : (int64_t)INT32_MAX;
+    int64_t qrun = 0, urun = 0, trun = 0;
     for (int s0 = 0; s0 < nsets; s0 += kWG) {
         const int s = s0 + (int)threadIdx.x;
         const int64_t c = s < nsets ? cnt[s] : 0;
-        int64_t tq, tu;
+        const int64_t units = (c + kGroup - 1) / kGroup;
+        const int64_t tasks = s < nsets ? units * dense_spans(sets[s].n, span) : 0;
+        int64_t tq, tu, tt;
         const int64_t eq = block_excl_scan<kWG>(c, sh, &tq);
-        const int64_t eu = block_excl_scan<kWG>((c + kGroup - 1) / kGroup, sh, &tu);
+        const int64_t eu = block_excl_scan<kWG>(units, sh, &tu);
+        const int64_t et = block_excl_scan<kWG>(tasks, sh, &tt);
         if (s < nsets) {
             off[s] = (int32_t)(qrun + eq);
             uoff[s] = (int32_t)(urun + eu);
+            toff[s] = (int32_t)(trun + et);
             fill[s] = 0;
         }
         qrun += tq;
         urun += tu;
+        trun += tt;
     }
     if (threadIdx.x == 0) {
         off[nsets] = (int32_t)qrun;
         uoff[nsets] = (int32_t)urun;
+        toff[nsets] = (int32_t)trun;
         ctl->nbunits = (uint32_t)urun;
+        ctl->nbtasks = (uint32_t)trun;
+        ctl->bspan = span;
     }
 }
 
@@ -1144,7 +1171,9 @@ __global__ __launch_bounds__(kWG) void k_brute_plan(int32_t* __restrict__ bset, 
 __global__ __launch_bounds__(kWG) void k_brute_group(const Chunk* __restrict__ blist,
                                                      const Ctl* __restrict__ ctl,
                                                      int32_t* __restrict__ bset, int nsets,
-                                                     int32_t* __restrict__ bq) {
+                                                     int32_t* __restrict__ bq,
+                                                     const double4* __restrict__ pos,
+                                                     int32_t* __restrict__ counts) {
     int32_t* fill = bset + nsets;
     const int32_t* off = bset + 2 * nsets;
     const uint32_t nb = ctl->nbrute;
@@ -1155,7 +1184,10 @@ __global__ __launch_bounds__(kWG) void k_brute_group(const Chunk* __restrict__ b
         int base = 0;
         if (lane == 0) base = atomicAdd(&fill[ch.set], ch.cnt);
         base = __shfl(base, 0, 64);
-        if (lane < ch.cnt) bq[off[ch.set] + base + lane] = ch.beg + lane;
+        if (lane < ch.cnt) {
+            bq[off[ch.set] + base + lane] = ch.beg + lane;
+            counts[(int)pos[ch.beg + lane].w] = 0;  // the count pass adds its spans
+        }
     }
 }
 
@@ -1163,10 +1195,11 @@ __global__ __launch_bounds__(kWG) void k_brute_group(const Chunk* __restrict__ b
 // query q of the unit): the set's particles, already in original index
 // order in `orig`, pass through shared memory in tiles of kDenseTile;
 // wavefront w tests its quarter of each tile with the FP64 predicate, one
-// bit per (query, candidate).  Count mode sums the bits; fill mode writes
-// each row in ascending index at offsets[i] plus the hits of the earlier
-// tiles and of the lower wavefronts.  Persistent over the units.
-constexpr int kDenseTile = 768;
+// bit per (query, candidate).  Count mode adds the bits of one span of the
+// set to the query's count; fill mode sweeps the whole set and writes each
+// row in ascending index at offsets[i] plus the hits of the earlier tiles
+// and of the lower wavefronts.  Persistent over the tasks (count) or units
+// (fill).
 constexpr int kDenseWords = kDenseTile / kWaves / 32;  // words per wavefront and tile
 
 template <int MODE>
@@ -1184,24 +1217,31 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
     __shared__ int32_t s_cnt[kWaves][64];
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     if (MODE == kFill && ((ctl->overflow & kOvfChunks) || offsets[n] > capacity)) return;
-    const uint32_t nu = ctl->nbunits;
     const int32_t* bcnt = bset;
     const int32_t* off = bset + 2 * nsets;
     const int32_t* uoff = off + nsets + 1;
+    const int32_t* toff = uoff + nsets + 1;
+    const int32_t* woff = MODE == kCount ? toff : uoff;  // first task / unit of each set
+    const uint32_t nwork = MODE == kCount ? ctl->nbtasks : ctl->nbunits;
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    for (uint32_t u = blockIdx.x; u < nu; u += gridDim.x) {
-        // Set of unit u: the last set whose first unit is at most u.
+    for (uint32_t u = blockIdx.x; u < nwork; u += gridDim.x) {
+        // Set of task u: the last set whose first task is at most u.
         int slo = 0, shi = nsets - 1;
         while (slo < shi) {
             const int mid = (slo + shi + 1) >> 1;
-            if ((uint32_t)uoff[mid] <= u) slo = mid;
+            if ((uint32_t)woff[mid] <= u) slo = mid;
             else shi = mid - 1;
         }
         const int set = slo;
-        const int j = (int)u - uoff[set];
-        const int qcnt = min(kGroup, bcnt[set] - kGroup * j);
         const int64_t jb = sets[set].beg, jn = sets[set].n;
+        const int64_t span = MODE == kCount ? ctl->bspan : jn;
+        const int64_t spans = MODE == kCount ? dense_spans(jn, span) : 1;
+        const int64_t local = (int64_t)u - woff[set];
+        const int j = (int)(local / spans);             // unit within the set
+        const int64_t c0 = (local % spans) * span;      // this task's candidates [c0, c1)
+        const int64_t c1 = MODE == kCount ? min(jn, c0 + span) : jn;
+        const int qcnt = min(kGroup, bcnt[set] - kGroup * j);
         const bool qv = lane < qcnt;
         const int qpos = qv ? bq[off[set] + kGroup * j + lane] : 0;
         const double4 qp = qv ? pos[qpos] : make_double4(0.0, 0.0, 0.0, 0.0);
@@ -1210,11 +1250,11 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
         const double r2 = qv ? __dmul_rn(R, R) : -1.0;  // nothing is below -1
         int64_t run = (MODE == kFill && qv) ? offsets[qidx] : 0;
         int64_t hits = 0;
-        for (int64_t t0 = 0; t0 < jn; t0 += kDenseTile) {
+        for (int64_t t0 = c0; t0 < c1; t0 += kDenseTile) {
             __syncthreads();  // the previous tile is no longer read
             for (int i = t; i < kDenseTile; i += kWG) {
                 const int64_t j = t0 + i;
-                s_c[i] = j < jn ? orig[jb + j] : make_double4(NAN, NAN, NAN, 0.0);
+                s_c[i] = j < c1 ? orig[jb + j] : make_double4(NAN, NAN, NAN, 0.0);
             }
             __syncthreads();
             uint32_t wd[kDenseWords];
@@ -1274,7 +1314,8 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
             s_cnt[w][lane] = (int)hits;
             __syncthreads();
             if (w == 0 && qv)
-                counts[qidx] = s_cnt[0][lane] + s_cnt[1][lane] + s_cnt[2][lane] + s_cnt[3][lane];
+                atomicAdd(&counts[qidx],
+                          s_cnt[0][lane] + s_cnt[1][lane] + s_cnt[2][lane] + s_cnt[3][lane]);
         }
         __syncthreads();
     }
@@ -1293,6 +1334,7 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
         ctl->nsplit3 = 0;
         ctl->nbrute = 0;
         ctl->nbunits = 0;
+        ctl->nbtasks = 0;
         ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
         ctl->overflow &= ~(kOvfScratch | kOvfCapacity | kOvfChunks | kOvfWalk);
         stats->pair_tests = 0;
@@ -1416,10 +1458,11 @@ void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets
     if (t.prm.precision == BTREE_FP32_FILTER) launch_split<true>(t, h, counts, st);
     else launch_split<false>(t, h, counts, st);
     hipLaunchKernelGGL(k_brute_plan, dim3(1), dim3(kWG), 0, st, t.bset.as<int32_t>(),
-                       (int)t.nsets, t.ctl.as<Ctl>());
+                       (int)t.nsets, t.sets.as<SetDev>(), t.ctl.as<Ctl>());
     BT_LAUNCH();
     hipLaunchKernelGGL(k_brute_group, dim3(kBruteGrid), dim3(kWG), 0, st, t.blist.as<Chunk>(),
-                       t.ctl.as<Ctl>(), t.bset.as<int32_t>(), (int)t.nsets, t.bq.as<int32_t>());
+                       t.ctl.as<Ctl>(), t.bset.as<int32_t>(), (int)t.nsets, t.bq.as<int32_t>(),
+                       t.pos.as<double4>(), counts);
     BT_LAUNCH();
     hipLaunchKernelGGL((k_dense<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets,
