@@ -36,7 +36,9 @@
 //        D > T_hi = (1 + g3)(1 + u)^2 (R(1 + 2^-48) + eta)^2    => not one
 //    (thresholds rounded outwards to FP32, with an absolute slack of
 //    8*2^-126 for flushed subnormals); pairs in between are decided by the
-//    FP64 predicate on the original coordinates.
+//    FP64 predicate on the original coordinates.  Items whose spread or
+//    radius reaches 2^60 (where FP32 squares could overflow) take FP64
+//    arithmetic.
 #include "prim.h"
 
 #include <algorithm>
@@ -533,7 +535,8 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         }
         const double sn = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) * up;
         const double rmax = wave_max(R);
-        unsafe = !(sn < 0x1p100 && rmax < 0x1p100);
+        // Every square, product and threshold below stays under 2^128.
+        unsafe = !(sn < 0x1p60 && rmax < 0x1p60);
         const double u = 0x1p-24;
         const double eta = (0x1p-24 + 0x1p-52) * sn * (1.0 + 0x1p-40) + 8.0 * 0x1p-126;
         const double g3 = 3.0 * u / (1.0 - 3.0 * u);

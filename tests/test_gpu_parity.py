@@ -216,6 +216,12 @@ def test_edge_cases(prec):
     z = z * 1e-3
     h = h * 1e-3
     assert_same_lists(gpu_lists(x, y, z, h, prec), oracle.lists(x, y, z, h))
+    # scales where FP32 squares overflow (2^70) or flush to zero (2^-70):
+    # the FP32 filter must hand such items to FP64 arithmetic
+    x, y, z, h = W.uniform_cube(3000, 5, 64.0)
+    for scale in (2.0 ** 70, 2.0 ** -70):
+        xs, ys, zs, hs = x * scale, y * scale, z * scale, h * scale
+        assert_same_lists(gpu_lists(xs, ys, zs, hs, prec), oracle.lists(xs, ys, zs, hs))
     # all zero h: every row empty
     x, y, z, h = W.uniform_cube(3000, 4, 64.0)
     got = gpu_lists(x, y, z, np.zeros(3000), prec)
