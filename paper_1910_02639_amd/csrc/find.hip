@@ -890,9 +890,16 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     if (w == 0 && qv) soff[qidx] = base + s_qoff[lane];
     // Rows: lane q of wavefront w writes the hits of its block right after
     // those of the blocks of lower wavefronts (ascending original index).
+    // Every lane writes a row of its own, so the stores are scattered: once
+    // the lane's position is 16-byte aligned it collects four entries and
+    // writes them with one store.  (Assembling the item's rows in shared
+    // memory for coalesced stores was slower: the extra barriers put every
+    // wavefront's extraction on the item's critical path.)
     if (qv) {
         int64_t at = base + s_qoff[lane];
         for (int k = 0; k < w; ++k) at += s_cnt[k][lane];
+        int32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
+        int nb = 0;
 #pragma unroll
         for (int i = 0; i < kMaxW; ++i) {
             const int wi = i - (kMaxW - nw);  // word index within the block
@@ -902,9 +909,33 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 while (word) {
                     const int j = __clz(word);
                     word &= ~(0x80000000u >> j);
-                    scratch[at++] = Ent<F32>::key(cand(kb + j)) - sbeg;
+                    const int32_t v = Ent<F32>::key(cand(kb + j)) - sbeg;
+                    if (nb == 0 && (at & 3)) {
+                        scratch[at++] = v;  // up to the first aligned position
+                        continue;
+                    }
+                    b0 = b1;
+                    b1 = b2;
+                    b2 = b3;
+                    b3 = v;
+                    if (++nb == 4) {
+                        *reinterpret_cast<int4*>(scratch + at) = make_int4(b0, b1, b2, b3);
+                        at += 4;
+                        nb = 0;
+                    }
                 }
             }
+        }
+        // The last one to three entries sit at the top of the buffer.
+        if (nb == 3) {
+            scratch[at] = b1;
+            scratch[at + 1] = b2;
+            scratch[at + 2] = b3;
+        } else if (nb == 2) {
+            scratch[at] = b2;
+            scratch[at + 1] = b3;
+        } else if (nb == 1) {
+            scratch[at] = b3;
         }
     }
     return 0;
