@@ -625,16 +625,40 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         }
     };
 
-    // Stage, pass 1: count candidates inside E per index bucket.
-    int myC = 0;
-    visit([&](const double4& P, bool in) {
-        if (in) {
-            const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
-            atomicAdd(&s_bcnt[bk], 1);
-        }
-        myC += __popcll(__ballot(in));
-    });
-    if (lane == 0) atomicAdd(&s_C, myC);
+    auto entry = [&](const double4& P) -> E {
+        if constexpr (F32)
+            return make_float4((float)(P.x - cx), (float)(P.y - cy), (float)(P.z - cz),
+                               __int_as_float((int)P.w));
+        else
+            return P;
+    };
+    auto bucket = [&](int key) { return min(kBuckets - 1, (int)((float)(key - kmin) * binv)); };
+    constexpr int kPer = (CMAX + kWG - 1) / kWG;
+    constexpr bool kPhys = kPer <= 6;  // six entries per thread fit in registers
+
+    // Stage, pass 1: count candidates inside E per index bucket.  With up to
+    // six entries per thread the candidates also go to shared memory here,
+    // in arrival order (past the budget they are only counted).
+    if constexpr (kPhys) {
+        visit([&](const double4& P, bool in) {
+            const uint64_t m = __ballot(in);
+            int b = 0;
+            if (lane == 0 && m) b = atomicAdd(&s_C, (int)__popcll(m));
+            b = __shfl(b, 0, 64);
+            if (in) {
+                atomicAdd(&s_bcnt[bucket((int)P.w)], 1);
+                const int slot = b + lanes_below(m);
+                if (slot < CMAX) s_cand[slot] = entry(P);
+            }
+        });
+    } else {
+        int myC = 0;
+        visit([&](const double4& P, bool in) {
+            if (in) atomicAdd(&s_bcnt[bucket((int)P.w)], 1);
+            myC += __popcll(__ballot(in));
+        });
+        if (lane == 0) atomicAdd(&s_C, myC);
+    }
     __syncthreads();
     const int C = __builtin_amdgcn_readfirstlane(s_C);
     if (C > CMAX) return C;
@@ -657,19 +681,32 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         if (P2 > CMAX) return C;
     }
 
-    // Stage, pass 2: place each candidate in its bucket.
-    visit([&](const double4& P, bool in) {
-        if (in) {
-            const int bk = min(kBuckets - 1, (int)((float)((int)P.w - kmin) * binv));
-            const int slot = atomicAdd(&s_bcur[bk], 1);
-            if constexpr (F32) {
-                s_cand[slot] = make_float4((float)(P.x - cx), (float)(P.y - cy),
-                                           (float)(P.z - cz), __int_as_float((int)P.w));
-            } else {
-                s_cand[slot] = P;
-            }
-        }
-    });
+    // Stage, pass 2: each candidate into its bucket; from shared memory
+    // through registers (all slots are taken before any entry is written),
+    // or, with the split kernels' larger budget, from global memory again.
+    if constexpr (kPhys) {
+        // Six named entries (an array here would leave registers).
+        auto take = [&](int p) -> E { return s_cand[p < C ? p : 0]; };
+        auto slot = [&](int p, const E e) -> int {
+            return p < C ? atomicAdd(&s_bcur[bucket(Ent<F32>::key(e))], 1) : -1;
+        };
+        const E v0 = take(t), v1 = take(t + kWG), v2 = take(t + 2 * kWG);
+        const E v3 = take(t + 3 * kWG), v4 = take(t + 4 * kWG), v5 = take(t + 5 * kWG);
+        const int s0 = slot(t, v0), s1 = slot(t + kWG, v1), s2 = slot(t + 2 * kWG, v2);
+        const int s3 = slot(t + 3 * kWG, v3), s4 = slot(t + 4 * kWG, v4);
+        const int s5 = slot(t + 5 * kWG, v5);
+        __syncthreads();
+        if (s0 >= 0) s_cand[s0] = v0;
+        if (s1 >= 0) s_cand[s1] = v1;
+        if (s2 >= 0) s_cand[s2] = v2;
+        if (s3 >= 0) s_cand[s3] = v3;
+        if (s4 >= 0) s_cand[s4] = v4;
+        if (s5 >= 0) s_cand[s5] = v5;
+    } else {
+        visit([&](const double4& P, bool in) {
+            if (in) s_cand[atomicAdd(&s_bcur[bucket((int)P.w)], 1)] = entry(P);
+        });
+    }
     __syncthreads();
 
     // Order by original index.  Keys are distinct, so a candidate's rank is
@@ -677,8 +714,6 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     // the main kernel's budget each entry then moves to its rank; with the
     // split kernel's larger one, s_perm[rank] = its slot instead.  An item
     // with a crowded bucket is sorted whole in place.
-    constexpr int kPer = (CMAX + kWG - 1) / kWG;
-    constexpr bool kPhys = kPer <= 6;  // the move below handles six entries per thread
     if (!s_big && kPhys) {
         // Entries move to their ranks through registers: all ranks are
         // taken before any entry is overwritten.
