@@ -1109,14 +1109,19 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
 }
 
 // Rows from the scratch into the CSR array (original order).  A wavefront
-// takes 64 consecutive rows; lane r loads row r's length, source and
-// destination, a prefix sum over the lanes numbers the entries of the 64
-// rows as one run, and every lane then copies entries e, e + 64, ... of that
-// run (four per lane per step), finding its row by a binary search over the
-// prefix held in the lanes.  So every lane moves data on every step however
-// the row lengths vary.  Rows taken by the exhaustive path (or without room
-// in the scratch) count as empty here.  Nothing is written when the rows do
-// not fit the caller's capacity.
+// takes 64 consecutive rows (lane r loads row r's length, source and
+// destination) and copies them four at a time with all its lanes, so every
+// load and store is coalesced and no lane searches for its row; the first
+// 128 entries of the four rows are loaded before any is stored, so that
+// eight loads per lane are in flight.  Rows taken by the exhaustive path
+// (or without room in the scratch) count as empty here.  Nothing is written
+// when the rows do not fit the caller's capacity.
+__device__ __forceinline__ int64_t readlane64(int64_t v, int j) {
+    const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, j);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), j);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ counts,
                                                const int64_t* __restrict__ soff,
                                                const int64_t* __restrict__ offsets,
@@ -1133,40 +1138,42 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
     const int64_t nw = ((int64_t)gridDim.x * kWG) >> 6;
     for (int64_t r0 = wid * 64; r0 < n; r0 += nw * 64) {
         const int64_t i = r0 + lane;
-        int64_t so = -1, o = 0;
+        int64_t so = 0, o = 0;
         int c = 0;
         if (i < n) {
             so = soff[i];
             o = offsets[i];
             c = so >= 0 ? counts[i] : 0;
+            if (so < 0) so = 0;
         }
-        const int inc = wave_incl_scan(c);
-        const int pre = inc - c;  // first entry of row `lane` in the run
-        const int total = __builtin_amdgcn_readfirstlane(__shfl(inc, 63, 64));
-        for (int e0 = 0; e0 < total; e0 += 4 * 64) {
-            int64_t src[4], dst[4];
-            bool ok[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int e = e0 + u * 64 + lane;
-                ok[u] = e < total;
-                // row j: the last lane whose first entry is <= e
-                int j = 0;
-#pragma unroll
-                for (int step = 32; step > 0; step >>= 1) {
-                    const int cand = j + step;
-                    if (__shfl(pre, cand, 64) <= e) j = cand;
-                }
-                const int k = e - __shfl(pre, j, 64);
-                src[u] = __shfl(so, j, 64) + k;
-                dst[u] = __shfl(o, j, 64) + k;
-            }
-            int32_t v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = ok[u] ? scratch[src[u]] : 0;
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (ok[u]) nbrs[dst[u]] = v[u];
+        for (int j0 = 0; j0 < 64; j0 += 4) {
+            const int c0 = __builtin_amdgcn_readlane(c, j0);
+            const int c1 = __builtin_amdgcn_readlane(c, j0 + 1);
+            const int c2 = __builtin_amdgcn_readlane(c, j0 + 2);
+            const int c3 = __builtin_amdgcn_readlane(c, j0 + 3);
+            if ((c0 | c1 | c2 | c3) == 0) continue;
+            const int64_t s0 = readlane64(so, j0), s1 = readlane64(so, j0 + 1);
+            const int64_t s2 = readlane64(so, j0 + 2), s3 = readlane64(so, j0 + 3);
+            const int64_t d0 = readlane64(o, j0), d1 = readlane64(o, j0 + 1);
+            const int64_t d2 = readlane64(o, j0 + 2), d3 = readlane64(o, j0 + 3);
+            const int ka = lane, kb = lane + 64;
+            const int32_t a0 = ka < c0 ? scratch[s0 + ka] : 0, b0 = kb < c0 ? scratch[s0 + kb] : 0;
+            const int32_t a1 = ka < c1 ? scratch[s1 + ka] : 0, b1 = kb < c1 ? scratch[s1 + kb] : 0;
+            const int32_t a2 = ka < c2 ? scratch[s2 + ka] : 0, b2 = kb < c2 ? scratch[s2 + kb] : 0;
+            const int32_t a3 = ka < c3 ? scratch[s3 + ka] : 0, b3 = kb < c3 ? scratch[s3 + kb] : 0;
+            if (ka < c0) nbrs[d0 + ka] = a0;
+            if (kb < c0) nbrs[d0 + kb] = b0;
+            if (ka < c1) nbrs[d1 + ka] = a1;
+            if (kb < c1) nbrs[d1 + kb] = b1;
+            if (ka < c2) nbrs[d2 + ka] = a2;
+            if (kb < c2) nbrs[d2 + kb] = b2;
+            if (ka < c3) nbrs[d3 + ka] = a3;
+            if (kb < c3) nbrs[d3 + kb] = b3;
+            // Entries past the first 128 of a row.
+            for (int k = lane + 128; k < c0; k += 64) nbrs[d0 + k] = scratch[s0 + k];
+            for (int k = lane + 128; k < c1; k += 64) nbrs[d1 + k] = scratch[s1 + k];
+            for (int k = lane + 128; k < c2; k += 64) nbrs[d2 + k] = scratch[s2 + k];
+            for (int k = lane + 128; k < c3; k += 64) nbrs[d3 + k] = scratch[s3 + k];
         }
     }
 }
