@@ -1102,6 +1102,7 @@ void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off_in, const btree_pa
     t.blist.reserve(sizeof(Chunk) * t.leaf_cap);
     t.bq.reserve(sizeof(int32_t) * nn);
     t.bset.reserve(sizeof(int32_t) * (5 * (int64_t)nsets + 3));
+    t.btab.reserve(sizeof(int32_t) * 64 * kDenseTaskCap);
     t.ctl.reserve(sizeof(Ctl));
     t.stats.reserve(sizeof(Stats));
     t.tot.reserve(sizeof(int64_t) * (nsets + 1));

@@ -193,6 +193,8 @@ struct Ctl {
     uint32_t nbunits;           // exhaustive-path units after regrouping by set
     uint32_t nbtasks;           // exhaustive count-pass tasks (unit x span of its set)
     int64_t bspan;              // candidates per exhaustive count-pass task
+    int32_t bfill_tasks;        // 1: the exhaustive fill pass also runs by tasks
+    int32_t pad_ctl;
 };
 
 // Allocation from the search's pools (row scratch, walk lists) goes through
@@ -200,6 +202,7 @@ struct Ctl {
 // 1/kStripes of the pool: one counter shared by every workgroup of the chip
 // would serialise its atomics.
 constexpr int kStripes = 64;
+constexpr int64_t kDenseTaskCap = 16384;  // exhaustive tasks whose counts the fill pass reuses
 constexpr int kStripeStride = 16;  // uint64 per cursor slot
 
 constexpr int kPersistBlocks = 2048;  // grid of the persistent per-cell / per-item kernels
@@ -301,6 +304,7 @@ struct Tree {
     DBuf blist;    // Chunk per unit (1 to 64 queries of one set) listed for the exhaustive path
     DBuf bq;       // tree positions of the exhaustive path's queries, grouped by set
     DBuf bset;     // per set: listed queries, fill cursor, query, unit and count-task offsets
+    DBuf btab;     // per exhaustive count task and lane: the lane's hits in the task's span
     DBuf scan_tmp; // scan block sums
     DBuf scratch;  // int32 rows of the search, in work-item order
     DBuf soff;     // int64 per particle: row start in scratch (-1: exhaustive path)

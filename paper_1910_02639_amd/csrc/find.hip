@@ -1239,6 +1239,7 @@ __global__ __launch_bounds__(kWG) void k_brute_plan(int32_t* __restrict__ bset, 
         ctl->nbunits = (uint32_t)urun;
         ctl->nbtasks = (uint32_t)trun;
         ctl->bspan = span;
+        ctl->bfill_tasks = trun <= kDenseTaskCap ? 1 : 0;
     }
 }
 
@@ -1272,15 +1273,17 @@ __global__ __launch_bounds__(kWG) void k_brute_group(const Chunk* __restrict__ b
 // order in `orig`, pass through shared memory in tiles of kDenseTile;
 // wavefront w tests its quarter of each tile with the FP64 predicate, one
 // bit per (query, candidate).  Count mode adds the bits of one span of the
-// set to the query's count; fill mode sweeps the whole set and writes each
-// row in ascending index at offsets[i] plus the hits of the earlier tiles
-// and of the lower wavefronts.  Persistent over the tasks (count) or units
-// (fill).
+// set to the query's count and, when the tasks fit kDenseTaskCap, records
+// it per task and lane; fill mode then runs by the same tasks and writes
+// each row in ascending index at offsets[i] plus the hits of the unit's
+// earlier spans, earlier tiles and lower wavefronts (else it sweeps the
+// whole set per unit).  Persistent over the tasks or units.
 constexpr int kDenseWords = kDenseTile / kWaves / 32;  // words per wavefront and tile
 
 template <int MODE>
 __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
                                                const int32_t* __restrict__ bset, int nsets,
+                                               int32_t* __restrict__ btab,
                                                const SetDev* __restrict__ sets,
                                                const double4* __restrict__ pos,
                                                const double4* __restrict__ orig,
@@ -1297,8 +1300,9 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
     const int32_t* off = bset + 2 * nsets;
     const int32_t* uoff = off + nsets + 1;
     const int32_t* toff = uoff + nsets + 1;
-    const int32_t* woff = MODE == kCount ? toff : uoff;  // first task / unit of each set
-    const uint32_t nwork = MODE == kCount ? ctl->nbtasks : ctl->nbunits;
+    const bool by_task = MODE == kCount || ctl->bfill_tasks;
+    const int32_t* woff = by_task ? toff : uoff;  // first task / unit of each set
+    const uint32_t nwork = by_task ? ctl->nbtasks : ctl->nbunits;
     const int t = threadIdx.x, lane = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     for (uint32_t u = blockIdx.x; u < nwork; u += gridDim.x) {
@@ -1311,12 +1315,13 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
         }
         const int set = slo;
         const int64_t jb = sets[set].beg, jn = sets[set].n;
-        const int64_t span = MODE == kCount ? ctl->bspan : jn;
-        const int64_t spans = MODE == kCount ? dense_spans(jn, span) : 1;
+        const int64_t span = by_task ? ctl->bspan : jn;
+        const int64_t spans = by_task ? dense_spans(jn, span) : 1;
         const int64_t local = (int64_t)u - woff[set];
         const int j = (int)(local / spans);             // unit within the set
-        const int64_t c0 = (local % spans) * span;      // this task's candidates [c0, c1)
-        const int64_t c1 = MODE == kCount ? min(jn, c0 + span) : jn;
+        const int64_t ks = local % spans;               // span within the unit
+        const int64_t c0 = ks * span;                   // this task's candidates [c0, c1)
+        const int64_t c1 = min(jn, c0 + span);
         const int qcnt = min(kGroup, bcnt[set] - kGroup * j);
         const bool qv = lane < qcnt;
         const int qpos = qv ? bq[off[set] + kGroup * j + lane] : 0;
@@ -1325,6 +1330,8 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
         const double R = qv ? 2.0 * h[qpos] : 0.0;
         const double r2 = qv ? __dmul_rn(R, R) : -1.0;  // nothing is below -1
         int64_t run = (MODE == kFill && qv) ? offsets[qidx] : 0;
+        if (MODE == kFill && by_task && qv)
+            for (int64_t k = 0; k < ks; ++k) run += btab[((int64_t)u - ks + k) * 64 + lane];
         int64_t hits = 0;
         for (int64_t t0 = c0; t0 < c1; t0 += kDenseTile) {
             __syncthreads();  // the previous tile is no longer read
@@ -1389,9 +1396,11 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
             __syncthreads();
             s_cnt[w][lane] = (int)hits;
             __syncthreads();
-            if (w == 0 && qv)
-                atomicAdd(&counts[qidx],
-                          s_cnt[0][lane] + s_cnt[1][lane] + s_cnt[2][lane] + s_cnt[3][lane]);
+            if (w == 0) {
+                const int tot = s_cnt[0][lane] + s_cnt[1][lane] + s_cnt[2][lane] + s_cnt[3][lane];
+                if (qv) atomicAdd(&counts[qidx], tot);
+                if (ctl->bfill_tasks) btab[(int64_t)u * 64 + lane] = qv ? tot : 0;
+            }
         }
         __syncthreads();
     }
@@ -1541,7 +1550,7 @@ void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets
                        t.pos.as<double4>(), counts);
     BT_LAUNCH();
     hipLaunchKernelGGL((k_dense<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
-                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets,
+                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
                        t.sets.as<SetDev>(), t.pos.as<double4>(),
                        t.orig.as<double4>(), t.hs.as<double>(), counts, nullptr, t.n, (int64_t)0, nullptr,
                        t.ctl.as<Ctl>());
@@ -1571,7 +1580,7 @@ void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* 
     BT_HIP(hipEventRecord(sd.fork, st));
     BT_HIP(hipStreamWaitEvent(sd.s, sd.fork, 0));
     hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, sd.s,
-                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets,
+                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
                        t.sets.as<SetDev>(), t.pos.as<double4>(), t.orig.as<double4>(),
                        t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs, t.ctl.as<Ctl>());
     BT_LAUNCH();

@@ -84,6 +84,26 @@ def test_split_paths(prec):
     assert 0 < st["brute_chunks"] <= 64 * len(h[::997])
 
 
+@pytest.mark.parametrize("prec", PRECS)
+def test_exhaustive_spans(prec):
+    """Queries whose box covers most of a set larger than one span of the
+    exhaustive count pass (9216 candidates): their rows are assembled from
+    five spans counted and filled by separate workgroups, and must equal
+    the oracle's."""
+    n = 40_000
+    x, y, z, h = W.uniform_cube(n, 11, 64.0)
+    h = h.copy()
+    big = np.arange(0, n, 200)
+    h[big] = 0.45
+    log("exhaustive spans", prec)
+    got = gpu_lists(x, y, z, h, prec, bucket_size=64)
+    check_csr_invariants(got[0], got[1], got[2], n)
+    assert got[3]["brute_chunks"] >= len(big)
+    rng = np.random.default_rng(3)
+    rows = np.unique(np.concatenate([big, rng.integers(0, n, 300)]))
+    assert_same_lists(got, oracle.lists(x, y, z, h, rows), rows)
+
+
 @pytest.mark.parametrize("name,s,kw", [("U10k", 64, {}), ("P60k", 32, {}),
                                        ("P60k", 16, {"beta": 0.2}), ("L1M", 128, {})])
 def test_tree_matches_algorithm1(name, s, kw):
