@@ -46,15 +46,6 @@ __global__ void k_fill_i32(int32_t* __restrict__ a, int64_t n, int32_t v) {
 }
 
 // Zeroes a[0 .. *len) and b[0 .. *len), the length read on the device.
-__global__ void k_zero2_dev(int32_t* __restrict__ a, int32_t* __restrict__ b,
-                            const int64_t* __restrict__ len) {
-    const int64_t n = *len;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        a[i] = 0;
-        b[i] = 0;
-    }
-}
 
 __global__ void k_ctl_reset(Ctl* __restrict__ ctl) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
@@ -225,22 +216,24 @@ __global__ void k_candidates(Node* __restrict__ nodes, const SetDev* __restrict_
     }
 }
 
-// Histogram length of the level; stop the build if it exceeds the pool.
-__global__ void k_hist_check(Ctl* __restrict__ ctl, const int64_t* __restrict__ hoff,
-                             int64_t cap) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Histogram length of the level (stop the build if it exceeds the pool),
+// and the histogram and slot cursors cleared up to it.  Every workgroup
+// derives the length itself; the first records it.
+__global__ void k_hist_zero(Ctl* __restrict__ ctl, const int64_t* __restrict__ hoff, int64_t cap,
+                            int32_t* __restrict__ hist, int32_t* __restrict__ cursor) {
     const int64_t m = ctl->lvm;
-    const int64_t len = hoff[m];
-    if (m == 0) {
-        ctl->level_ok = 0;
-        ctl->hist_len = 0;
-    } else if (len > cap) {
-        ctl->overflow |= kOvfHist;
-        ctl->level_ok = 0;
-        ctl->hist_len = 0;
-    } else {
-        ctl->level_ok = 1;
-        ctl->hist_len = len;
+    const int64_t len = m > 0 ? hoff[m] : 0;
+    const bool ok = m > 0 && len <= cap;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (m > 0 && !ok) ctl->overflow |= kOvfHist;
+        ctl->level_ok = ok ? 1 : 0;
+        ctl->hist_len = ok ? len : 0;
+    }
+    if (!ok) return;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        hist[i] = 0;
+        cursor[i] = 0;
     }
 }
 
@@ -1107,7 +1100,8 @@ void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off_in, const btree_pa
     t.stats.reserve(sizeof(Stats));
     t.tot.reserve(sizeof(int64_t) * (nsets + 1));
     t.soff.reserve(sizeof(int64_t) * nn);
-    scan_reserve(t, std::max<int64_t>(std::max<int64_t>(nc, t.leaf_cap), 256 * rtiles + 1));
+    scan_reserve(t, std::max<int64_t>(std::max<int64_t>(3 * nc + 4 * 2048, t.leaf_cap),
+                                      256 * rtiles + 1));
     scan_reserve(t, nn + 1);
 }
 
@@ -1161,11 +1155,9 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
                            t.sets.as<SetDev>(), ctl, W.hsize.as<int64_t>());
         BT_LAUNCH();
         scan_dev_i64(W.hsize.as<int64_t>(), W.hoff.as<int64_t>(), &ctl->lvm, nc, t, st);
-        hipLaunchKernelGGL(k_hist_check, dim3(1), dim3(64), 0, st, ctl, W.hoff.as<int64_t>(),
-                           t.hist_cap);
-        BT_LAUNCH();
-        hipLaunchKernelGGL(k_zero2_dev, dim3(kPersistBlocks), dim3(256), 0, st, W.hist.as<int32_t>(),
-                           W.cursor.as<int32_t>(), &ctl->hist_len);
+        hipLaunchKernelGGL(k_hist_zero, dim3(kPersistBlocks), dim3(256), 0, st, ctl,
+                           W.hoff.as<int64_t>(), t.hist_cap, W.hist.as<int32_t>(),
+                           W.cursor.as<int32_t>());
         BT_LAUNCH();
         hipLaunchKernelGGL(k_histogram, dim3(gR), dim3(kT), 0, st, Ps[par]->as<double4>(),
                            Ns[par]->as<int32_t>(), n, t.nodes.as<Node>(), ctl, W.hoff.as<int64_t>(),
@@ -1180,9 +1172,9 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
                            W.hist.as<int32_t>(), W.cstart.as<int32_t>(), W.crank.as<int32_t>(),
                            W.nint.as<int64_t>(), W.nleaf.as<int64_t>(), W.ctsize.as<int64_t>());
         BT_LAUNCH();
-        scan_dev_i64(W.nint.as<int64_t>(), W.ibase.as<int64_t>(), &ctl->lvm, nc, t, st);
-        scan_dev_i64(W.nleaf.as<int64_t>(), W.lbase.as<int64_t>(), &ctl->lvm, nc, t, st);
-        scan_dev_i64(W.ctsize.as<int64_t>(), W.ctoff.as<int64_t>(), &ctl->lvm, nc, t, st);
+        scan3_dev_i64(W.nint.as<int64_t>(), W.ibase.as<int64_t>(), W.nleaf.as<int64_t>(),
+                      W.lbase.as<int64_t>(), W.ctsize.as<int64_t>(), W.ctoff.as<int64_t>(),
+                      &ctl->lvm, nc, t, st);
         hipLaunchKernelGGL(k_level_alloc, dim3(1), dim3(64), 0, st, ctl, W.ibase.as<int64_t>(),
                            W.lbase.as<int64_t>(), W.ctoff.as<int64_t>(), t.node_cap, t.leaf_cap,
                            t.ctab_cap);

@@ -449,6 +449,11 @@ void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, Tree& t,
 void radix_sort_pairs(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n, int bits,
                       Tree& t, DBuf& cnt, DBuf& off, hipStream_t st);
 void scan_reserve(Tree& t, int64_t ncap);
+// Three device-length int64 scans of one length in one launch sequence;
+// needs scan_reserve(t, 3 * ncap + 4 * 2048).
+void scan3_dev_i64(const int64_t* in0, int64_t* out0, const int64_t* in1, int64_t* out1,
+                   const int64_t* in2, int64_t* out2, const int32_t* nptr, int64_t ncap,
+                   Tree& t, hipStream_t st);
 void scan_dev_i32(const int32_t* in, int64_t* out, const int32_t* nptr, int64_t ncap, Tree& t,
                   hipStream_t st);
 void scan_dev_i64(const int64_t* in, int64_t* out, const int32_t* nptr, int64_t ncap, Tree& t,

@@ -153,7 +153,100 @@ void scan_dev_impl(const In* in, int64_t* out, const int32_t* nptr, int64_t ncap
     BT_LAUNCH();
 }
 
+// Three arrays of one device length scanned together (three launches for
+// the three): tile sums and tile scans of array k go to tsum[k * (ntiles+1)].
+struct Scan3 {
+    const int64_t* in[3];
+    int64_t* out[3];
+};
+
+__global__ __launch_bounds__(kT) void k_tile_sum_dev3(Scan3 a, const int32_t* __restrict__ nptr,
+                                                      int64_t* __restrict__ tsum, int64_t ntiles) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    const int64_t n = *nptr;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        int64_t s = 0;
+        if (base < n) {
+#pragma unroll
+            for (int i = 0; i < kItems; ++i) {
+                const int64_t k = base + i * kT + threadIdx.x;
+                if (k < n) s += a.in[q][k];
+            }
+            s = block_sum<kT>(s, sh);
+        }
+        if (threadIdx.x == 0) tsum[q * (ntiles + 1) + blockIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_scan_tiles3(int64_t* __restrict__ tsum, int64_t ntiles) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    for (int q = 0; q < 3; ++q) {
+        int64_t* ts = tsum + q * (ntiles + 1);
+        int64_t carry = 0;
+        for (int64_t b0 = 0; b0 < ntiles; b0 += kT) {
+            const int64_t k = b0 + threadIdx.x;
+            const int64_t v = k < ntiles ? ts[k] : 0;
+            int64_t tot;
+            const int64_t ex = block_excl_scan<kT>(v, sh, &tot);
+            if (k < ntiles) ts[k] = carry + ex;
+            carry += tot;
+        }
+        if (threadIdx.x == 0) ts[ntiles] = carry;
+    }
+}
+
+__global__ __launch_bounds__(kT) void k_tile_scan_dev3(Scan3 a, const int32_t* __restrict__ nptr,
+                                                       const int64_t* __restrict__ tsum,
+                                                       int64_t ntiles) {
+    __shared__ int64_t sh[kT / 64 + 1];
+    const int64_t n = *nptr;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        const int64_t* ts = tsum + q * (ntiles + 1);
+        if (blockIdx.x == 0 && threadIdx.x == 0) a.out[q][n] = ts[ntiles];
+        if ((int64_t)blockIdx.x * kTile >= n) continue;  // uniform over the workgroup
+        const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+        int64_t v[kItems];
+        int64_t s = 0;
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int64_t k = base + i;
+            v[i] = k < n ? a.in[q][k] : 0;
+            s += v[i];
+        }
+        int64_t tot;
+        int64_t ex = block_excl_scan<kT>(s, sh, &tot) + ts[blockIdx.x];
+#pragma unroll
+        for (int i = 0; i < kItems; ++i) {
+            const int64_t k = base + i;
+            if (k < n) a.out[q][k] = ex;
+            ex += v[i];
+        }
+    }
+}
+
 }  // namespace
+
+void scan3_dev_i64(const int64_t* in0, int64_t* out0, const int64_t* in1, int64_t* out1,
+                   const int64_t* in2, int64_t* out2, const int32_t* nptr, int64_t ncap,
+                   Tree& t, hipStream_t st) {
+    int64_t ntiles = (ncap + kTile - 1) / kTile;
+    if (ntiles < 1) ntiles = 1;
+    if (t.scan_tmp.bytes < sizeof(int64_t) * (size_t)(3 * (ntiles + 1)))
+        fail(BTREE_EDEVICE, "scan workspace not reserved");
+    int64_t* ts = t.scan_tmp.as<int64_t>();
+    const Scan3 a{{in0, in1, in2}, {out0, out1, out2}};
+    hipLaunchKernelGGL(k_tile_sum_dev3, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
+                       ntiles);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_scan_tiles3, dim3(1), dim3(kT), 0, st, ts, ntiles);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_tile_scan_dev3, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
+                       ntiles);
+    BT_LAUNCH();
+}
 
 void scan_reserve(Tree& t, int64_t ncap) {
     int64_t ntiles = (ncap + kTile - 1) / kTile;
