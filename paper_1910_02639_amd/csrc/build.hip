@@ -162,12 +162,8 @@ __global__ void k_roots(SetDev* __restrict__ sets, int nsets, Node* __restrict__
 __global__ __launch_bounds__(kT) void k_gather(const double4* __restrict__ orig,
                                                const int32_t* __restrict__ perm,
                                                const Tile* __restrict__ tiles,
-                                               const SetDev* __restrict__ sets,
-                                               double4* __restrict__ P0,
-                                               int32_t* __restrict__ pnode) {
+                                               double4* __restrict__ P0) {
     const Tile T = tiles[blockIdx.x];
-    const int32_t root = sets[T.set].root;
-    const int32_t pn = (root != kEmpty && !(root & kLeafBit)) ? root : -1;
     // Eight particles per thread and step, so that eight independent
     // index -> particle load chains are in flight.
     constexpr int kU = 8;
@@ -187,7 +183,6 @@ __global__ __launch_bounds__(kT) void k_gather(const double4* __restrict__ orig,
             if (i[u] < 0) continue;
             const int64_t k = k0 + u * kT;
             P0[k] = make_double4(q[u].x, q[u].y, q[u].z, (double)i[u]);
-            pnode[k] = pn;
         }
     }
 }
@@ -196,11 +191,24 @@ __global__ __launch_bounds__(kT) void k_gather(const double4* __restrict__ orig,
 // Level kernels.  The cells of the level are nodes [cur_nb, cur_ne).
 // ---------------------------------------------------------------------------
 
-// Step 1: histogram size of all branching candidates of each cell.  The
-// cell's b field holds the first candidate (Eq. 1) until k_select replaces
-// it with the chosen one.
+// The histogram and scatter kernels take tasks of up to kRunR consecutive
+// particles of one cell (the particles follow the Morton curve inside each
+// cell).  The cell's bins, up to kLdsBins / kLdsHistBins of them, are
+// counted in shared memory and added to global memory once per task; the
+// other bins use global atomics, one per distinct bin and wavefront.
+// Without this, the coarse bins of a large cell (b = 2: eight bins for
+// millions of particles) serialise millions of same-address atomics.
+constexpr int kRunPer = 8;
+constexpr int kRunR = kT * kRunPer;
+constexpr int kLdsBins = 8192;      // scatter: int32 counters
+constexpr int kLdsHistBins = 16384;  // histogram: two 16-bit counters per word (<= kRunR each)
+
+// Step 1: histogram size of all branching candidates of each cell, and its
+// number of particle tasks.  The cell's b field holds the first candidate
+// (Eq. 1) until k_select replaces it with the chosen one.
 __global__ void k_candidates(Node* __restrict__ nodes, const SetDev* __restrict__ sets,
-                             const Ctl* __restrict__ ctl, int64_t* __restrict__ hsize) {
+                             const Ctl* __restrict__ ctl, int64_t* __restrict__ hsize,
+                             int64_t* __restrict__ tcnt) {
     const int64_t nb = ctl->cur_nb, m = ctl->lvm;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -213,6 +221,7 @@ __global__ void k_candidates(Node* __restrict__ nodes, const SetDev* __restrict_
             if (bb == 2) break;
         }
         hsize[i] = sum;
+        tcnt[i] = ((int64_t)N.n + kRunR - 1) / kRunR;
     }
 }
 
@@ -237,20 +246,16 @@ __global__ void k_hist_zero(Ctl* __restrict__ ctl, const int64_t* __restrict__ h
     }
 }
 
-// The histogram and scatter kernels take kRunR consecutive particles per
-// workgroup.  The particles follow the Morton curve inside each cell, so
-// most of a workgroup's particles lie in one cell, its home cell (the cell of
-// the middle particle).  The home cell's bins, up to kLdsBins of them, are
-// counted in shared memory and added to global memory once per workgroup;
-// the other particles use global atomics, one per distinct bin and
-// wavefront.  Without this, the coarse bins of a large cell (b = 2: eight
-// bins for millions of particles) serialise millions of same-address
-// atomics.
-constexpr int kRunPer = 8;
-constexpr int kRunR = kT * kRunPer;
-constexpr int kLdsBins = 8192;      // scatter: int32 counters
-constexpr int kLdsHistBins = 16384;  // histogram: two 16-bit counters per word (<= kRunR each)
-static_assert(kRunR < 65536, "a workgroup's count per bin must fit 16 bits");
+// Cell of task u of the level: the last cell whose first task is at most u.
+__device__ __forceinline__ int64_t task_cell(const int64_t* __restrict__ toff, int64_t m, int64_t u) {
+    int64_t lo = 0, hi = m - 1;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi + 1) >> 1;
+        if (toff[mid] <= u) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
 
 // Adds 1 per active lane to a 16-bit counter packed two to a word in shared
 // memory.  A wavefront whose active lanes all hit one bin adds with one
@@ -268,7 +273,7 @@ __device__ __forceinline__ void lds_inc16(uint32_t* w, int32_t bin, bool active)
     }
 }
 
-// Rank of each active lane among the workgroup's particles of its bin, from
+// Rank of each active lane among the task's particles of its bin, from
 // int32 counters in shared memory (one atomic when the wavefront's active
 // lanes share one bin).
 __device__ __forceinline__ int32_t lds_rank(int32_t* cnt, int32_t bin, bool active) {
@@ -285,89 +290,69 @@ __device__ __forceinline__ int32_t lds_rank(int32_t* cnt, int32_t bin, bool acti
     return active ? atomicAdd(&cnt[bin], 1) : 0;
 }
 
-// Home cell of the workgroup's range starting at `base`, or -1.
-__device__ __forceinline__ int32_t home_cell(const int32_t* __restrict__ pnode, int64_t base,
-                                             int64_t n, int32_t nb, int32_t ne) {
-    if (base >= n) return -1;
-    const int64_t mid = min(base + kRunR / 2, n - 1);
-    const int32_t h = pnode[mid];
-    return (h >= nb && h < ne) ? h : -1;
-}
+static_assert(kRunR < 65536, "a task's count per bin must fit 16 bits");
 
-// Step 2: one histogram per candidate b (Eqs. 2 and 3).
+// Step 2: one histogram per candidate b (Eqs. 2 and 3), persistent over the
+// level's tasks.  Shared window: the last kLdsHistBins bins of the cell's
+// candidates (the small b, whose bins are the crowded ones).
 __global__ __launch_bounds__(kT) void k_histogram(const double4* __restrict__ P,
-                                                  const int32_t* __restrict__ pnode, int64_t n,
                                                   const Node* __restrict__ nodes,
                                                   const Ctl* __restrict__ ctl,
                                                   const int64_t* __restrict__ hoff,
+                                                  const int64_t* __restrict__ toff,
                                                   int32_t* __restrict__ hist) {
     if (!ctl->level_ok) return;
     __shared__ uint32_t s_bin[kLdsHistBins / 2];
-    const int32_t nb = ctl->cur_nb, ne = ctl->cur_ne;
-    const int64_t base = (int64_t)blockIdx.x * kRunR;
-    // Shared window: the last kLdsHistBins bins of the home cell's
-    // candidates (the small b, whose bins are the crowded ones).
-    const int32_t home = home_cell(pnode, base, n, nb, ne);
-    int64_t wlo = 0;
-    int32_t wlen = 0;
-    if (home >= 0) {
-        const int64_t h0 = hoff[home - nb], h1 = hoff[home - nb + 1];
-        wlo = max(h0, h1 - kLdsHistBins);
-        wlen = (int32_t)(h1 - wlo);
-    }
-    const int32_t wwords = (wlen + 1) >> 1;
-    for (int i = threadIdx.x; i < wwords; i += kT) s_bin[i] = 0;
-    __syncthreads();
-    int32_t node[kRunPer];
-#pragma unroll
-    for (int j = 0; j < kRunPer; ++j) {
-        const int64_t p = base + j * kT + threadIdx.x;
-        node[j] = p < n ? pnode[p] : -1;
-    }
-#pragma unroll 1
-    for (int j = 0; j < kRunPer; ++j) {
-        const int64_t p = base + j * kT + threadIdx.x;
-        const bool act = node[j] >= nb && node[j] < ne;
-        double tx = 0.0, ty = 0.0, tz = 0.0;
-        int64_t off = 0;
-        int bb = 2, ncand = 0;
-        if (act) {
-            const double4 q = P[p];
-            const Node& N = nodes[node[j]];
-            // Eq. 2 fractions per axis: the same for every candidate b.
-            tx = subcell_frac(q.x, N.lo[0], N.hi[0]);
-            ty = subcell_frac(q.y, N.lo[1], N.hi[1]);
-            tz = subcell_frac(q.z, N.lo[2], N.hi[2]);
-            off = hoff[node[j] - nb];
-            bb = N.b;  // Eq. 1, set by k_candidates
-            for (int b = bb;; b = halve(b)) {
-                ++ncand;
-                if (b == 2) break;
-            }
+    const int32_t nb = ctl->cur_nb;
+    const int64_t m = ctl->lvm;
+    const int64_t ntask = toff[m];
+    for (int64_t u = blockIdx.x; u < ntask; u += gridDim.x) {
+        const int64_t ci = task_cell(toff, m, u);
+        const Node& N = nodes[nb + ci];
+        const int64_t p0 = (int64_t)N.beg + (u - toff[ci]) * kRunR;
+        const int64_t p1 = min((int64_t)N.beg + N.n, p0 + kRunR);
+        const int64_t h0 = hoff[ci], h1 = hoff[ci + 1];
+        const int64_t wlo = max(h0, h1 - kLdsHistBins);
+        const int32_t wwords = (int32_t)((h1 - wlo + 1) >> 1);
+        const int b0 = N.b;  // Eq. 1, set by k_candidates
+        int ncand = 0;
+        for (int b = b0;; b = halve(b)) {
+            ++ncand;
+            if (b == 2) break;
         }
-        const bool mine = act && node[j] == home;
-        int maxc = ncand;
-#pragma unroll
-        for (int d = 32; d > 0; d >>= 1) maxc = max(maxc, __shfl_xor(maxc, d, 64));
-        for (int k = 0; k < maxc; ++k) {
-            const bool a = act && k < ncand;
-            int64_t key = 0;
-            if (a) {
-                key = off + subcell_of(tx, bb) +
-                      (int64_t)bb * (subcell_of(ty, bb) + (int64_t)bb * subcell_of(tz, bb));
+        __syncthreads();  // the previous task's flush is done with s_bin
+        for (int i = threadIdx.x; i < wwords; i += kT) s_bin[i] = 0;
+        __syncthreads();
+#pragma unroll 1
+        for (int j = 0; j < kRunPer; ++j) {
+            const int64_t p = p0 + j * kT + threadIdx.x;
+            const bool act = p < p1;
+            double tx = 0.0, ty = 0.0, tz = 0.0;
+            if (act) {
+                const double4 q = P[p];
+                // Eq. 2 fractions per axis: the same for every candidate b.
+                tx = subcell_frac(q.x, N.lo[0], N.hi[0]);
+                ty = subcell_frac(q.y, N.lo[1], N.hi[1]);
+                tz = subcell_frac(q.z, N.lo[2], N.hi[2]);
+            }
+            int64_t off = h0;
+            int bb = b0;
+            for (int k = 0; k < ncand; ++k) {
+                const int64_t key = off + subcell_of(tx, bb) +
+                                    (int64_t)bb * (subcell_of(ty, bb) + (int64_t)bb * subcell_of(tz, bb));
                 off += (int64_t)bb * bb * bb;
                 bb = halve(bb);
+                const bool local = act && key >= wlo;
+                lds_inc16(s_bin, (int32_t)(key - wlo), local);
+                wave_agg_inc(hist, key, act && !local);
             }
-            const bool local = a && mine && key >= wlo;
-            lds_inc16(s_bin, (int32_t)(key - wlo), local);
-            wave_agg_inc(hist, key, a && !local);
         }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < wwords; i += kT) {
-        const uint32_t v = s_bin[i];
-        if (v & 0xffffu) atomicAdd(&hist[wlo + 2 * i], (int32_t)(v & 0xffffu));
-        if (v >> 16) atomicAdd(&hist[wlo + 2 * i + 1], (int32_t)(v >> 16));
+        __syncthreads();
+        for (int i = threadIdx.x; i < wwords; i += kT) {
+            const uint32_t v = s_bin[i];
+            if (v & 0xffffu) atomicAdd(&hist[wlo + 2 * i], (int32_t)(v & 0xffffu));
+            if (v >> 16) atomicAdd(&hist[wlo + 2 * i + 1], (int32_t)(v >> 16));
+        }
     }
 }
 
@@ -583,90 +568,80 @@ __global__ __launch_bounds__(kT) void k_emit(Node* __restrict__ nodes,
     }
 }
 
-// Step 5: scatter each particle of a cell into its sub-cell segment.  Home
-// cell particles (when the cell's b^3 fits kLdsBins) take a rank in their
-// sub-cell from shared counters, and each sub-cell reserves its slots for
-// the workgroup with one global atomic; the others take slots per wavefront
-// and sub-cell.
+// Step 5: scatter each particle of a cell into its sub-cell segment,
+// persistent over the level's tasks.  When the cell's b^3 fits kLdsBins,
+// particles take a rank in their sub-cell from shared counters and each
+// sub-cell reserves the task's slots with one global atomic; otherwise slots
+// are taken per wavefront and sub-cell.  Particles that end in leaves stay
+// in the destination array, those of next-level cells are read from it by
+// the next level.
 __global__ __launch_bounds__(kT) void k_scatter(const double4* __restrict__ Psrc,
                                                 double4* __restrict__ Pdst,
-                                                const int32_t* __restrict__ pn_src,
-                                                int32_t* __restrict__ pn_dst, int64_t n,
                                                 const Node* __restrict__ nodes,
                                                 const Ctl* __restrict__ ctl,
                                                 const int32_t* __restrict__ bsel,
                                                 const int64_t* __restrict__ selofs,
                                                 const int32_t* __restrict__ cstart,
                                                 int32_t* __restrict__ cursor,
-                                                const int32_t* __restrict__ ctab) {
+                                                const int64_t* __restrict__ toff, int64_t n) {
     if (!ctl->level_ok) return;
-    __shared__ int32_t s_cnt[kLdsBins];  // counts, then the workgroup's first slot
-    const int32_t nb = ctl->cur_nb, ne = ctl->cur_ne;
-    const int64_t base = (int64_t)blockIdx.x * kRunR;
-    const int32_t home = home_cell(pn_src, base, n, nb, ne);
-    int64_t wlo = 0;
-    int32_t wlen = 0;
-    if (home >= 0) {
-        const int b = bsel[home - nb];
-        if ((int64_t)b * b * b <= kLdsBins) {
-            wlo = selofs[home - nb];
-            wlen = b * b * b;
-        }
-    }
-    for (int i = threadIdx.x; i < wlen; i += kT) s_cnt[i] = 0;
-    __syncthreads();
-    // Home particles wait in registers for their sub-cell's slots.
-    double4 q[kRunPer];
-    int64_t dst[kRunPer];  // start of the sub-cell's segment; -1: nothing pending
-    int32_t code[kRunPer], bin[kRunPer], rank[kRunPer];
+    __shared__ int32_t s_cnt[kLdsBins];  // counts, then the task's first slot
+    const int32_t nb = ctl->cur_nb;
+    const int64_t m = ctl->lvm;
+    const int64_t ntask = toff[m];
+    for (int64_t u = blockIdx.x; u < ntask; u += gridDim.x) {
+        const int64_t ci = task_cell(toff, m, u);
+        const Node& N = nodes[nb + ci];
+        const int64_t p0 = (int64_t)N.beg + (u - toff[ci]) * kRunR;
+        const int64_t p1 = min((int64_t)N.beg + N.n, p0 + kRunR);
+        const int b = bsel[ci];
+        const int64_t sel = selofs[ci];
+        const int32_t wlen = (int64_t)b * b * b <= kLdsBins ? b * b * b : 0;
+        __syncthreads();  // the previous task is done with s_cnt
+        for (int i = threadIdx.x; i < wlen; i += kT) s_cnt[i] = 0;
+        __syncthreads();
+        // Particles with a shared-memory rank wait in registers for their
+        // sub-cell's first slot.
+        double4 q[kRunPer];
+        int64_t dst[kRunPer];  // start of the sub-cell's segment; -1: nothing pending
+        int32_t bin[kRunPer], rank[kRunPer];
 #pragma unroll
-    for (int j = 0; j < kRunPer; ++j) {
-        const int64_t p = base + j * kT + threadIdx.x;
-        const int32_t node = p < n ? pn_src[p] : -1;
-        const bool act = node >= nb && node < ne;
-        int64_t key = 0, start = 0;
-        int32_t c = 0, cd = -1;
-        double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
-        if (act) {
-            const Node& N = nodes[node];
-            const int64_t i = node - nb;
-            const int b = bsel[i];
-            v = Psrc[p];
-            const int cx = subcell(v.x, N.lo[0], N.hi[0], b);
-            const int cy = subcell(v.y, N.lo[1], N.hi[1], b);
-            const int cz = subcell(v.z, N.lo[2], N.hi[2], b);
-            c = cx + b * (cy + b * cz);
-            key = selofs[i] + c;
-            start = (int64_t)N.beg + cstart[key];
-            cd = ctab[N.ctab + c];
+        for (int j = 0; j < kRunPer; ++j) {
+            const int64_t p = p0 + j * kT + threadIdx.x;
+            const bool act = p < p1;
+            int64_t key = 0, start = 0;
+            int32_t c = 0;
+            double4 v = make_double4(0.0, 0.0, 0.0, 0.0);
+            if (act) {
+                v = Psrc[p];
+                const int cx = subcell(v.x, N.lo[0], N.hi[0], b);
+                const int cy = subcell(v.y, N.lo[1], N.hi[1], b);
+                const int cz = subcell(v.z, N.lo[2], N.hi[2], b);
+                c = cx + b * (cy + b * cz);
+                key = sel + c;
+                start = (int64_t)N.beg + cstart[key];
+            }
+            const bool local = act && wlen > 0;
+            dst[j] = local ? start : -1;
+            q[j] = v;
+            bin[j] = c;
+            rank[j] = lds_rank(s_cnt, c, local);
+            const int32_t slot = wave_agg_slot(cursor, key, act && !local);
+            if (act && !local) Pdst[start + slot] = v;
         }
-        const bool local = act && wlen > 0 && node == home;
-        dst[j] = -1;
-        q[j] = v;
-        code[j] = (cd & kLeafBit) ? -1 : cd;
-        bin[j] = c;
-        rank[j] = lds_rank(s_cnt, c, local);
-        if (local) dst[j] = start;
-        const int32_t slot = wave_agg_slot(cursor, key, act && !local);
-        if (act && !local) {
-            const int64_t d = start + slot;
-            Pdst[d] = v;
-            pn_dst[d] = code[j];
+        __syncthreads();
+        for (int i = threadIdx.x; i < wlen; i += kT) {
+            const int32_t v = s_cnt[i];
+            if (v) s_cnt[i] = atomicAdd(&cursor[sel + i], v);
         }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < wlen; i += kT) {
-        const int32_t v = s_cnt[i];
-        if (v) s_cnt[i] = atomicAdd(&cursor[wlo + i], v);
-    }
-    __syncthreads();
+        __syncthreads();
 #pragma unroll
-    for (int j = 0; j < kRunPer; ++j) {
-        if (dst[j] < 0) continue;
-        const int64_t d = dst[j] + s_cnt[bin[j]] + rank[j];
-        if ((uint64_t)d >= (uint64_t)n) continue;  // cannot happen; keeps a slot error off memory
-        Pdst[d] = q[j];
-        pn_dst[d] = code[j];
+        for (int j = 0; j < kRunPer; ++j) {
+            if (dst[j] < 0) continue;
+            const int64_t d = dst[j] + s_cnt[bin[j]] + rank[j];
+            if ((uint64_t)d >= (uint64_t)n) continue;  // cannot happen; keeps a slot error off memory
+            Pdst[d] = q[j];
+        }
     }
 }
 
@@ -1049,8 +1024,6 @@ void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off_in, const btree_pa
     const int64_t nn = std::max<int64_t>(n, 1);
     W.P0.reserve(sizeof(double4) * nn);
     W.P1.reserve(sizeof(double4) * nn);
-    W.pn0.reserve(sizeof(int32_t) * nn);
-    W.pn1.reserve(sizeof(int32_t) * nn);
     W.part.reserve(sizeof(double) * 6 * std::max<int64_t>(t.ntiles, 1));
     W.mk0.reserve(sizeof(uint32_t) * nn);
     W.mk1.reserve(sizeof(uint32_t) * nn);
@@ -1061,6 +1034,8 @@ void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off_in, const btree_pa
     W.roff.reserve(sizeof(int64_t) * (256 * rtiles + 1));
     const int64_t nc = t.node_cap;
     W.hsize.reserve(sizeof(int64_t) * nc);
+    W.tcnt.reserve(sizeof(int64_t) * nc);
+    W.toff.reserve(sizeof(int64_t) * (nc + 1));
     W.hoff.reserve(sizeof(int64_t) * (nc + 1));
     W.bsel.reserve(sizeof(int32_t) * nc);
     W.selofs.reserve(sizeof(int64_t) * nc);
@@ -1138,29 +1113,30 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
         radix_sort_pairs(W.mk0.as<uint32_t>(), W.mv0.as<int32_t>(), W.mk1.as<uint32_t>(),
                          W.mv1.as<int32_t>(), n, 32, t, W.rcnt, W.roff, st);
         hipLaunchKernelGGL(k_gather, dim3(nt), dim3(kT), 0, st, t.orig.as<double4>(),
-                           W.mv0.as<int32_t>(), W.tiles.as<Tile>(), t.sets.as<SetDev>(),
-                           W.P0.as<double4>(), W.pn0.as<int32_t>());
+                           W.mv0.as<int32_t>(), W.tiles.as<Tile>(), W.P0.as<double4>());
         BT_LAUNCH();
     }
 
     DBuf* Ps[2] = {&W.P0, &W.P1};
-    DBuf* Ns[2] = {&W.pn0, &W.pn1};
     const unsigned gN = grid_for(std::max<int64_t>(n, 1), kT);
-    const unsigned gR = grid_for(std::max<int64_t>(n, 1), kRunR);
+    // Histogram and scatter: persistent over the level's tasks.
+    const unsigned gR =
+        (unsigned)std::min<int64_t>(kPersistBlocks, std::max<int64_t>(1, (n + kRunR - 1) / kRunR));
     const int64_t nc = t.node_cap;
     int level = 0;
     for (; level < levels; ++level) {
         const int par = level & 1;
         hipLaunchKernelGGL(k_candidates, dim3(kPersistBlocks), dim3(256), 0, st, t.nodes.as<Node>(),
-                           t.sets.as<SetDev>(), ctl, W.hsize.as<int64_t>());
+                           t.sets.as<SetDev>(), ctl, W.hsize.as<int64_t>(), W.tcnt.as<int64_t>());
         BT_LAUNCH();
-        scan_dev_i64(W.hsize.as<int64_t>(), W.hoff.as<int64_t>(), &ctl->lvm, nc, t, st);
+        scan2_dev_i64(W.hsize.as<int64_t>(), W.hoff.as<int64_t>(), W.tcnt.as<int64_t>(),
+                      W.toff.as<int64_t>(), &ctl->lvm, nc, t, st);
         hipLaunchKernelGGL(k_hist_zero, dim3(kPersistBlocks), dim3(256), 0, st, ctl,
                            W.hoff.as<int64_t>(), t.hist_cap, W.hist.as<int32_t>(),
                            W.cursor.as<int32_t>());
         BT_LAUNCH();
         hipLaunchKernelGGL(k_histogram, dim3(gR), dim3(kT), 0, st, Ps[par]->as<double4>(),
-                           Ns[par]->as<int32_t>(), n, t.nodes.as<Node>(), ctl, W.hoff.as<int64_t>(),
+                           t.nodes.as<Node>(), ctl, W.hoff.as<int64_t>(), W.toff.as<int64_t>(),
                            W.hist.as<int32_t>());
         BT_LAUNCH();
         hipLaunchKernelGGL(k_select, dim3(kPersistBlocks), dim3(kT), 0, st, t.nodes.as<Node>(),
@@ -1186,10 +1162,9 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
                            t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.ldepth.as<int32_t>());
         BT_LAUNCH();
         hipLaunchKernelGGL(k_scatter, dim3(gR), dim3(kT), 0, st, Ps[par]->as<double4>(),
-                           Ps[par ^ 1]->as<double4>(), Ns[par]->as<int32_t>(),
-                           Ns[par ^ 1]->as<int32_t>(), n, t.nodes.as<Node>(), ctl,
+                           Ps[par ^ 1]->as<double4>(), t.nodes.as<Node>(), ctl,
                            W.bsel.as<int32_t>(), W.selofs.as<int64_t>(), W.cstart.as<int32_t>(),
-                           W.cursor.as<int32_t>(), t.ctab.as<int32_t>());
+                           W.cursor.as<int32_t>(), W.toff.as<int64_t>(), n);
         BT_LAUNCH();
         hipLaunchKernelGGL(k_level_advance, dim3(1), dim3(64), 0, st, ctl, level, levels);
         BT_LAUNCH();

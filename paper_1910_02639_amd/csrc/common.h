@@ -209,7 +209,8 @@ constexpr int kPersistBlocks = 2048;  // grid of the persistent per-cell / per-i
 
 // Build workspace, kept by the handle so that rebuilds reuse its memory.
 struct Work {
-    DBuf P0, P1, pn0, pn1, part;
+    DBuf P0, P1, part;
+    DBuf tcnt, toff;  // per cell of a level: particle chunks, and their offsets
     DBuf hsize, hoff, hist, cstart, crank, cursor, bsel, selofs, nint, nleaf, ibase, lbase,
         ctsize, ctoff;
     DBuf mark, f, rank, newid, nc, coff;
@@ -449,8 +450,10 @@ void scan_exclusive_i64(const int64_t* in, int64_t* out, int64_t n, Tree& t,
 void radix_sort_pairs(uint32_t* k0, int32_t* v0, uint32_t* k1, int32_t* v1, int64_t n, int bits,
                       Tree& t, DBuf& cnt, DBuf& off, hipStream_t st);
 void scan_reserve(Tree& t, int64_t ncap);
-// Three device-length int64 scans of one length in one launch sequence;
-// needs scan_reserve(t, 3 * ncap + 4 * 2048).
+// Two or three device-length int64 scans of one length in one launch
+// sequence; need scan_reserve(t, 3 * ncap + 4 * 2048).
+void scan2_dev_i64(const int64_t* in0, int64_t* out0, const int64_t* in1, int64_t* out1,
+                   const int32_t* nptr, int64_t ncap, Tree& t, hipStream_t st);
 void scan3_dev_i64(const int64_t* in0, int64_t* out0, const int64_t* in1, int64_t* out1,
                    const int64_t* in2, int64_t* out2, const int32_t* nptr, int64_t ncap,
                    Tree& t, hipStream_t st);

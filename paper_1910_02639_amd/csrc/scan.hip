@@ -153,20 +153,22 @@ void scan_dev_impl(const In* in, int64_t* out, const int32_t* nptr, int64_t ncap
     BT_LAUNCH();
 }
 
-// Three arrays of one device length scanned together (three launches for
-// the three): tile sums and tile scans of array k go to tsum[k * (ntiles+1)].
-struct Scan3 {
-    const int64_t* in[3];
-    int64_t* out[3];
+// K arrays of one device length scanned together (three launches for all
+// K): tile sums and tile scans of array q go to tsum[q * (ntiles+1)].
+template <int K>
+struct ScanK {
+    const int64_t* in[K];
+    int64_t* out[K];
 };
 
-__global__ __launch_bounds__(kT) void k_tile_sum_dev3(Scan3 a, const int32_t* __restrict__ nptr,
+template <int K>
+__global__ __launch_bounds__(kT) void k_tile_sum_devk(ScanK<K> a, const int32_t* __restrict__ nptr,
                                                       int64_t* __restrict__ tsum, int64_t ntiles) {
     __shared__ int64_t sh[kT / 64 + 1];
     const int64_t n = *nptr;
     const int64_t base = (int64_t)blockIdx.x * kTile;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < K; ++q) {
         int64_t s = 0;
         if (base < n) {
 #pragma unroll
@@ -180,9 +182,10 @@ __global__ __launch_bounds__(kT) void k_tile_sum_dev3(Scan3 a, const int32_t* __
     }
 }
 
-__global__ __launch_bounds__(kT) void k_scan_tiles3(int64_t* __restrict__ tsum, int64_t ntiles) {
+template <int K>
+__global__ __launch_bounds__(kT) void k_scan_tilesk(int64_t* __restrict__ tsum, int64_t ntiles) {
     __shared__ int64_t sh[kT / 64 + 1];
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < K; ++q) {
         int64_t* ts = tsum + q * (ntiles + 1);
         int64_t carry = 0;
         for (int64_t b0 = 0; b0 < ntiles; b0 += kT) {
@@ -197,13 +200,14 @@ __global__ __launch_bounds__(kT) void k_scan_tiles3(int64_t* __restrict__ tsum, 
     }
 }
 
-__global__ __launch_bounds__(kT) void k_tile_scan_dev3(Scan3 a, const int32_t* __restrict__ nptr,
+template <int K>
+__global__ __launch_bounds__(kT) void k_tile_scan_devk(ScanK<K> a, const int32_t* __restrict__ nptr,
                                                        const int64_t* __restrict__ tsum,
                                                        int64_t ntiles) {
     __shared__ int64_t sh[kT / 64 + 1];
     const int64_t n = *nptr;
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
+    for (int q = 0; q < K; ++q) {
         const int64_t* ts = tsum + q * (ntiles + 1);
         if (blockIdx.x == 0 && threadIdx.x == 0) a.out[q][n] = ts[ntiles];
         if ((int64_t)blockIdx.x * kTile >= n) continue;  // uniform over the workgroup
@@ -227,25 +231,34 @@ __global__ __launch_bounds__(kT) void k_tile_scan_dev3(Scan3 a, const int32_t* _
     }
 }
 
+template <int K>
+void scank_dev_i64(const ScanK<K>& a, const int32_t* nptr, int64_t ncap, Tree& t, hipStream_t st) {
+    int64_t ntiles = (ncap + kTile - 1) / kTile;
+    if (ntiles < 1) ntiles = 1;
+    if (t.scan_tmp.bytes < sizeof(int64_t) * (size_t)(K * (ntiles + 1)))
+        fail(BTREE_EDEVICE, "scan workspace not reserved");
+    int64_t* ts = t.scan_tmp.as<int64_t>();
+    hipLaunchKernelGGL(k_tile_sum_devk<K>, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
+                       ntiles);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_scan_tilesk<K>, dim3(1), dim3(kT), 0, st, ts, ntiles);
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_tile_scan_devk<K>, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
+                       ntiles);
+    BT_LAUNCH();
+}
+
 }  // namespace
+
+void scan2_dev_i64(const int64_t* in0, int64_t* out0, const int64_t* in1, int64_t* out1,
+                   const int32_t* nptr, int64_t ncap, Tree& t, hipStream_t st) {
+    scank_dev_i64<2>(ScanK<2>{{in0, in1}, {out0, out1}}, nptr, ncap, t, st);
+}
 
 void scan3_dev_i64(const int64_t* in0, int64_t* out0, const int64_t* in1, int64_t* out1,
                    const int64_t* in2, int64_t* out2, const int32_t* nptr, int64_t ncap,
                    Tree& t, hipStream_t st) {
-    int64_t ntiles = (ncap + kTile - 1) / kTile;
-    if (ntiles < 1) ntiles = 1;
-    if (t.scan_tmp.bytes < sizeof(int64_t) * (size_t)(3 * (ntiles + 1)))
-        fail(BTREE_EDEVICE, "scan workspace not reserved");
-    int64_t* ts = t.scan_tmp.as<int64_t>();
-    const Scan3 a{{in0, in1, in2}, {out0, out1, out2}};
-    hipLaunchKernelGGL(k_tile_sum_dev3, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
-                       ntiles);
-    BT_LAUNCH();
-    hipLaunchKernelGGL(k_scan_tiles3, dim3(1), dim3(kT), 0, st, ts, ntiles);
-    BT_LAUNCH();
-    hipLaunchKernelGGL(k_tile_scan_dev3, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
-                       ntiles);
-    BT_LAUNCH();
+    scank_dev_i64<3>(ScanK<3>{{in0, in1, in2}, {out0, out1, out2}}, nptr, ncap, t, st);
 }
 
 void scan_reserve(Tree& t, int64_t ncap) {
