@@ -455,7 +455,10 @@ constexpr int kNoCount = kHuge + 1;  // overflow of the leaf list, candidates no
 
 // WALK: 0 = walk here; 1 = take the walk kernel's list of item ci; 2 = take
 // it when ci >= 0 and the list is whole and fits, else walk here.
-template <bool F32, int WALK, int CMAX = kCMax, int LMAX = kLMax>
+constexpr int kSubGroup = 8;  // queries per sub-item of a split work item
+
+// SMALL: units of at most kSubGroup queries test with lane = candidate.
+template <bool F32, int WALK, int CMAX = kCMax, int LMAX = kLMax, bool SMALL = false>
 __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                                           const int4* __restrict__ whdr,
                                           const int2* __restrict__ wl,
@@ -783,6 +786,56 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     // Candidate k in index order.
     auto cand = [&](int k) -> E { return kPhys ? s_cand[k] : s_cand[s_perm[k]]; };
 
+    // A unit of at most kSubGroup queries (split levels 2 and 3) would use
+    // that many lanes of each wavefront in the layout below.  It tests with
+    // lane = candidate instead: for each query in turn, wavefront w takes its
+    // quarter of the 64-candidate chunks, a ballot gives the chunk's hits in
+    // index order, and a lane prefix places them in the row.  Counts first;
+    // the rows pass tests again (cheap at this size).
+    const bool small = SMALL && ch.cnt <= kSubGroup;
+    const int nch = (C + 63) >> 6;
+    const int ch0 = (nch * w) / kWaves, ch1 = (nch * (w + 1)) / kWaves;  // this wavefront's chunks
+    // Query q's data, broadcast from lane q by the whole wavefront (a
+    // cross-lane read from a lane that is inactive returns 0, so this is
+    // never done under a branch).
+    struct Q {
+        double x, y, z, R, r2;
+        float ax, ay, az, lo, hi;
+    };
+    auto query = [&](int q) -> Q {
+        return Q{__shfl(qp.x, q, 64), __shfl(qp.y, q, 64), __shfl(qp.z, q, 64), __shfl(R, q, 64),
+                 __shfl(r2q, q, 64),  __shfl(ax, q, 64),   __shfl(ay, q, 64),   __shfl(az, q, 64),
+                 __shfl(tlo, q, 64),  __shfl(thi, q, 64)};
+    };
+    // Hits of query Qd among chunk c.
+    auto chunk_hits = [&](const Q& Qd, int c, unsigned long long& nconf) -> uint64_t {
+        const int k = c * 64 + lane;
+        const bool v = k < C;
+        const E e = cand(v ? k : 0);
+        if constexpr (F32) {
+            const float tx = Qd.ax - e.x, ty = Qd.ay - e.y, tz = Qd.az - e.z;
+            const float D = fmaf(tz, tz, fmaf(ty, ty, tx * tx));
+            uint64_t lo = __ballot(v && D < Qd.lo);
+            const uint64_t band = __ballot(v && D < Qd.hi) & ~lo;
+            if (band) {
+                nconf += __popcll(band);
+                bool ok = false;
+                if ((band >> lane) & 1) {
+                    const double4 o = orig[Ent<F32>::key(e)];
+                    ok = p64(Qd.x, Qd.y, Qd.z, Qd.R, o.x, o.y, o.z);
+                }
+                lo |= __ballot(ok);
+            }
+            return lo;
+        } else {
+            const double dx = __dsub_rn(Qd.x, e.x), dy = __dsub_rn(Qd.y, e.y);
+            const double dz = __dsub_rn(Qd.z, e.z);
+            const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                        __dmul_rn(dz, dz));
+            return __ballot(v && d2 < Qd.r2);
+        }
+    };
+
     // Test: wavefront w sweeps candidates [k0, k1) (32-aligned) for its 64
     // queries; one bit per (query, candidate), first candidate in the top
     // bit of each 32-candidate word.  FP32 form: `word` collects D < T_lo
@@ -801,7 +854,16 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     for (int i = 0; i < kMaxW; ++i) wq[i] = 0u;
     int hits = 0;
     unsigned long long conf = 0;
-    for (int kw = k0; kw < k1; kw += 32) {
+    if (small) {
+        if (lane >= ch.cnt) s_cnt[w][lane] = 0;
+        for (int q = 0; q < ch.cnt; ++q) {
+            const Q Qd = query(q);
+            int hq = 0;
+            for (int c = ch0; c < ch1; ++c) hq += __popcll(chunk_hits(Qd, c, conf));
+            if (lane == 0) s_cnt[w][q] = hq;
+        }
+    }
+    for (int kw = k0; !small && kw < k1; kw += 32) {
         const int m = min(32, k1 - kw);
         uint32_t word = 0;
         if constexpr (F32) {
@@ -891,7 +953,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         wq[kMaxW - 1] = word;
     }
     if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
-    s_cnt[w][lane] = hits;
+    if (!small) s_cnt[w][lane] = hits;
     __syncthreads();
 
     // Row lengths, then one scratch allocation for the item.
@@ -923,6 +985,22 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         return 0;
     }
     if (w == 0 && qv) soff[qidx] = base + s_qoff[lane];
+    if (small) {
+        unsigned long long unused = 0;
+        const uint64_t below = (1ull << lane) - 1ull;
+        for (int q = 0; q < ch.cnt; ++q) {
+            const Q Qd = query(q);
+            int64_t at = base + s_qoff[q];
+            for (int k = 0; k < w; ++k) at += s_cnt[k][q];
+            for (int c = ch0; c < ch1; ++c) {
+                const uint64_t m = chunk_hits(Qd, c, unused);
+                if ((m >> lane) & 1)
+                    scratch[at + __popcll(m & below)] = Ent<F32>::key(cand(c * 64 + lane)) - sbeg;
+                at += __popcll(m);
+            }
+        }
+        return 0;
+    }
     // Rows: lane q of wavefront w writes the hits of its block right after
     // those of the blocks of lower wavefronts (ascending original index).
     // Every lane writes a row of its own, so the stores are scattered: once
@@ -1018,7 +1096,6 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     }
 }
 
-constexpr int kSubGroup = 8;  // queries per sub-item of a split work item
 // Shared-memory budget of the split kernel: it runs rarely, so it trades
 // occupancy for capacity (FP32 form 64 KB of candidates, FP64 form 96 KB).
 template <bool F32> constexpr int kCMaxSplit = F32 ? 4096 : 3072;
@@ -1094,7 +1171,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         }
         // Level 1 takes the item whole: its walk list, if whole, still holds.
         const int ci = LEVEL == 1 ? split_ci[u] : -1;
-        const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit>(
+        const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2)>(
             ci, unit, whdr, wl, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
             scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
         if (!C) continue;
