@@ -2,26 +2,27 @@
 //
 // Work item: up to 64 consecutive particles of one leaf (the paper's
 // blocked, cache-reusing search, recast for a GPU: a leaf's particles share
-// one tree walk and one staged candidate set).  A workgroup of 4 wavefronts
-// takes one work item; lane q of every wavefront holds query q.
+// one tree walk and one staged candidate set).  Pass 1 writes every query's
+// count and its row to a scratch buffer; pass 2 places the rows into the
+// caller's CSR arrays once the offsets are known.
 //
-//  1. Box E = [min_i fl(x_i - 2h_i), max_i fl(x_i + 2h_i)] of the item.
-//  2. Walk (Algorithm 2 with Eq. 5 applied to E): from the root, each
-//     internal cell's sub-cell range on every axis is [f(E_lo), f(E_hi)]
-//     with the build's own Eq. 2 function f; leaves in range go to a
-//     candidate list, internal sub-cells to a stack, all in LDS.
-//  3. Stage: the particles of the candidate leaves that lie inside E are
-//     compacted into LDS (wavefront ballot + lane prefix).  Every true
-//     neighbour of every query of the item lies inside E.
-//  4. Test: wavefront w sweeps its quarter of the staged candidates for its
-//     64 queries, LDS reads broadcast to all lanes.
-//  5. Count pass: per-query counts.  Fill pass: the staged candidates are
-//     first sorted by original index; hits are recorded as one bit per
-//     (query, candidate) in LDS, then each lane walks its bits in order and
-//     writes its row, which therefore comes out in ascending index.
-// Items whose candidate set does not fit the LDS budget (or whose walk
-// overflows its stack) are flagged in the count pass and handled by an
-// exhaustive FP64 sweep in original index order.
+//  1. k_walk, one wavefront per item: box E = [min_i fl(x_i - 2h_i),
+//     max_i fl(x_i + 2h_i)]; walk (Algorithm 2 with Eq. 5 applied to E),
+//     breadth first: each internal cell's sub-cell range on every axis is
+//     [f(E_lo), f(E_hi)] with the build's own Eq. 2 function f.  The
+//     candidate leaves go to a pool in global memory.
+//  2. k_sweep, one workgroup of 4 wavefronts per item (lane q of every
+//     wavefront holds query q): the particles of the candidate leaves that
+//     lie inside E are staged into LDS (every true neighbour of every query
+//     lies inside E) and put in original index order; wavefront w sweeps
+//     its quarter of them for its 64 queries (LDS reads broadcast to all
+//     lanes), one bit per (query, candidate); each lane then writes its row
+//     in ascending index to the scratch.
+//  3. Items whose candidates do not fit the LDS budget are searched again
+//     by k_sweep_split (the whole item with a larger budget, then parts of
+//     8 queries, then single queries), and what still does not fit by an
+//     exhaustive FP64 sweep of the query's set in index order (k_dense).
+//  4. k_place copies the rows into the CSR arrays (pass 2).
 //
 // Two arithmetic forms of the pair test, with identical results:
 //  * FP64: the exact predicate ((dx*dx + dy*dy) + dz*dz) < (2h)*(2h).
