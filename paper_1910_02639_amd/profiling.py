@@ -27,12 +27,17 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
 def source_hash():
-    """Hash of the search kernel sources the traffic figures belong to."""
+    """Hash of the search kernel sources the traffic figures belong to, over
+    their code only (line comments and blank lines do not count)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in ("find.hip", "common.h", "prim.h"):
-        with open(os.path.join(ROOT, "paper_1910_02639_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1910_02639_amd", "csrc", f)) as fh:
+            for line in fh:
+                code = re.sub(r"//.*", "", line).strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 
