@@ -92,8 +92,8 @@ typedef struct {
        calls since btree_build (btree_rebuild keeps counting):
        [0] build, [1] search sweep kernel (walk, stage, test, rows to the
        handle's scratch), [2] placement kernel (rows into the caller's CSR;
-       in the batched form the whole placement segment, whose exhaustive
-       rows run beside it), [3] whole pass 1, [4] whole pass 2;
+       in the batched form the whole placement segment, exhaustive rows
+       included), [3] whole pass 1, [4] whole pass 2;
        phase_calls counts the calls.                                      */
     double  phase_ms[5];
     int64_t phase_calls[5];
@@ -211,10 +211,9 @@ btree_status btree_batch_create(int32_t nsets, const int64_t* set_offsets,
  * The work is a captured HIP graph, recorded on the first call with a given
  * set of pointers and capacity and replayed on later calls with the same
  * ones: five graph segments (build; search set-up; sweep; counts and
- * offsets; row placement with the exhaustive rows beside it on a second
- * stream of the handle, then totals) launched back to back on hip_stream
- * with no host work between them (so that HIP events between segments can
- * time the steps).  The first call on a handle first runs an
+ * offsets; exhaustive rows, row placement and totals) launched back to
+ * back on hip_stream with no host work between them (so that HIP events
+ * between segments can time the steps).  The first call on a handle first runs an
  * eager build and count pass to size the pools.  The call waits for the
  * stream.  When a pool proves too small for new data, the handle grows it,
  * records the graph again and repeats the run.

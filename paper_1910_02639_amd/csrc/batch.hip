@@ -89,7 +89,6 @@ void capture(Batch& B, const double* x, const double* y, const double* z, const 
              int32_t* counts, int64_t* offsets, int32_t* nbrs, int64_t capacity) {
     Tree& t = B.t;
     B.drop_graph();
-    t.side.ensure();  // the placement segment forks onto it; not created while capturing
     record(B, kSegBuild, [&](hipStream_t s) { build_queue(t, x, y, z, (int)t.level_cap, false, s); });
     record(B, kSegBegin, [&](hipStream_t s) {
         find_begin(t, h, s);

@@ -261,25 +261,6 @@ struct Timer {
     }
 };
 
-// A second stream of the handle, forked from and joined back to the
-// caller's stream with two events, for work that can run beside the main
-// sequence (also inside a graph capture: the fork and join become edges).
-// Created outside any capture.  Default priority.
-struct SideStream {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, join = nullptr;
-    void ensure() {
-        if (!s) BT_HIP(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        if (!fork) BT_HIP(hipEventCreateWithFlags(&fork, hipEventDisableTiming));
-        if (!join) BT_HIP(hipEventCreateWithFlags(&join, hipEventDisableTiming));
-    }
-    ~SideStream() {
-        if (fork) (void)hipEventDestroy(fork);
-        if (join) (void)hipEventDestroy(join);
-        if (s) (void)hipStreamDestroy(s);
-    }
-};
-
 // The handle.
 struct Tree {
     int64_t n = 0;
@@ -315,7 +296,6 @@ struct Tree {
     DBuf wl;       // int2 pool: candidate leaves (first particle, count) of every item
     Work ws;
     Timer timer;
-    SideStream side;
 
     int64_t n_internal = 0, n_leaves = 0, n_chunks = 0, ctab_len = 0;
     int64_t scap = 0;  // scratch capacity, entries

@@ -1261,8 +1261,9 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
 // sweep they are regrouped by set into full units, so that every lane of
 // the sweep has a query.  The count pass cuts each unit's sweep over its set
 // into spans of kDenseSpan candidates, one workgroup each, so that a large
-// set does not make one workgroup the critical path; the fill pass (which
-// runs beside the placement) takes each unit whole.  `bset` holds, for
+// set does not make one workgroup the critical path; the fill pass uses the
+// same spans when their counts fit the task table (else whole units).
+// `bset` holds, for
 // nsets sets: listed queries [0, nsets), fill cursors [nsets, 2 nsets),
 // query offsets [2 nsets, 3 nsets + 1), unit offsets [3 nsets + 1,
 // 4 nsets + 2) and count-task offsets [4 nsets + 2, 5 nsets + 3).
@@ -1646,27 +1647,20 @@ void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t*
     BT_LAUNCH();
 }
 
-// Pass 2: the rows from the scratch into the caller's CSR (k_place, bound by
-// HBM) and, beside it on the handle's side stream, the rows of the
-// exhaustive path (a few workgroups bound by arithmetic); the two write
-// disjoint rows.  Then the per-set totals, when asked for.  `time_place`
-// times k_place alone (not inside a graph capture).
+// Pass 2: the rows of the exhaustive path, then the rows from the scratch
+// into the caller's CSR (k_place, bound by HBM); the two write disjoint
+// rows.  Then the per-set totals, when asked for.  `time_place` times
+// k_place alone (not inside a graph capture).
 void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
                int64_t capacity, int64_t* totals, bool time_place, hipStream_t st) {
-    SideStream& sd = t.side;
-    sd.ensure();
-    BT_HIP(hipEventRecord(sd.fork, st));
-    BT_HIP(hipStreamWaitEvent(sd.s, sd.fork, 0));
-    hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, sd.s,
+    hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
                        t.sets.as<SetDev>(), t.pos.as<double4>(), t.orig.as<double4>(),
                        t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs, t.ctl.as<Ctl>());
     BT_LAUNCH();
-    BT_HIP(hipEventRecord(sd.join, sd.s));
     if (time_place) t.timer.start(kPhPlace, st);
     find_place(t, counts, offsets, nbrs, capacity, st);
     if (time_place) t.timer.stop(kPhPlace, st);
-    BT_HIP(hipStreamWaitEvent(st, sd.join, 0));
     if (totals) {
         hipLaunchKernelGGL(k_set_totals, dim3(grid_for(t.nsets, 256)), dim3(256), 0, st, offsets,
                            t.sets.as<SetDev>(), t.nsets, totals);

@@ -260,3 +260,25 @@ def test_tuner_picks_a_candidate_and_results_do_not_depend_on_it():
             c, o, nb, totals = B.find(dx, dy, dz, dh)
             _check_batch([(x, y, z, h)], *_host(c, o, nb), totals)
     assert want[1][-1] == totals[0]
+
+
+def test_batch_handles_release_memory():
+    """Creating, running and closing batch handles returns their device
+    memory: free memory after the third cycle is within 256 MiB of the
+    first (a handle of this size holds about 1 GiB)."""
+    import torch
+    from paper_1910_02639_amd import btree
+    x, y, z, h = W.plummer(2_000_000, 4, 100.0)
+    dx, dy, dz, dh = to_dev(x, y, z, h)
+    log("batch memory release")
+    free = []
+    for _ in range(3):
+        B = btree.Batch([len(x)], [dict(bucket_size=64)])
+        c, o, nb, _ = B.find(dx, dy, dz, dh)
+        del c, o, nb
+        B.close()
+        del B
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        free.append(torch.cuda.mem_get_info()[0])
+    assert free[2] >= free[0] - 256 * 2 ** 20, free
