@@ -220,6 +220,16 @@ def test_edge_cases(prec):
     got = gpu_lists(x, y, z, h, prec, bucket_size=16, max_depth=12)
     assert_same_lists(got, oracle.lists(x, y, z, h))
     assert got[3]["oversized"] >= 1
+    # leaves of 700 and 1500 coincident particles at the depth guard: the
+    # workgroup sort (513..1024 particles) and the order-keeping copy above
+    for m in (700, 1500):
+        x = np.concatenate([np.full(m, 0.3), rng.random(500)])
+        y = np.concatenate([np.full(m, 0.6), rng.random(500)])
+        z = np.concatenate([np.full(m, 0.2), rng.random(500)])
+        h = np.full(m + 500, 0.02)
+        got = gpu_lists(x, y, z, h, prec, bucket_size=16, max_depth=6)
+        assert_same_lists(got, oracle.lists(x, y, z, h))
+        assert got[3]["max_leaf"] >= m
     # a plane (zero extent along z) and a line
     x, y = rng.random((2, 3000))
     z = np.zeros(3000)
