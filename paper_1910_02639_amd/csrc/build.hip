@@ -659,32 +659,40 @@ __global__ void k_level_advance(Ctl* __restrict__ ctl, int level, int level_cap)
 // After the levels: leaves in memory order, sorted, and cut into work items.
 // ---------------------------------------------------------------------------
 
-__global__ void k_mark_leaves(const Leaf* __restrict__ leaves, const Ctl* __restrict__ ctl,
-                              int32_t* __restrict__ mark) {
+// Leaves in particle order.  Every leaf is non-empty and leaves do not
+// overlap, so their first particles are distinct: one bit per particle marks
+// them, and a leaf's new id is the number of marks before its own (a scan
+// over the words' bit counts, then a count inside the word).
+__global__ void k_mark_bits(const Leaf* __restrict__ leaves, const Ctl* __restrict__ ctl,
+                            uint32_t* __restrict__ bits) {
     const int64_t nl = ctl->n_leaves;
     for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl;
-         l += (int64_t)gridDim.x * blockDim.x)
-        mark[leaves[l].beg] = (int32_t)l;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t p = leaves[l].beg;
+        atomicOr(&bits[p >> 5], 1u << (p & 31));
+    }
 }
 
-__global__ void k_mark_flags(const int32_t* __restrict__ mark, int64_t n, int32_t* __restrict__ f) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) f[p] = mark[p] >= 0 ? 1 : 0;
+__global__ void k_popc(const uint32_t* __restrict__ bits, int64_t nw, int32_t* __restrict__ pc) {
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nw;
+         k += (int64_t)gridDim.x * blockDim.x)
+        pc[k] = __popc(bits[k]);
 }
 
-// New id of every leaf = rank of its first particle; permute the table.
-__global__ void k_relabel_leaves(const int32_t* __restrict__ mark, const int64_t* __restrict__ rank,
-                                 int64_t n, const Leaf* __restrict__ lin,
+__global__ void k_relabel_leaves(const uint32_t* __restrict__ bits, const int64_t* __restrict__ pre,
+                                 const Ctl* __restrict__ ctl, const Leaf* __restrict__ lin,
                                  const int32_t* __restrict__ din, Leaf* __restrict__ lout,
                                  int32_t* __restrict__ dout, int32_t* __restrict__ newid) {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int32_t old = mark[p];
-    if (old < 0) return;
-    const int64_t r = rank[p];
-    lout[r] = lin[old];
-    dout[r] = din[old];
-    newid[old] = (int32_t)r;
+    const int64_t nl = ctl->n_leaves;
+    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl;
+         l += (int64_t)gridDim.x * blockDim.x) {
+        const Leaf L = lin[l];
+        const int32_t w = L.beg >> 5;
+        const int64_t r = pre[w] + __popc(bits[w] & ((1u << (L.beg & 31)) - 1u));
+        lout[r] = L;
+        dout[r] = din[l];
+        newid[l] = (int32_t)r;
+    }
 }
 
 __global__ void k_relabel_ctab(int32_t* __restrict__ ctab, const Ctl* __restrict__ ctl,
@@ -1118,7 +1126,6 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
     }
 
     DBuf* Ps[2] = {&W.P0, &W.P1};
-    const unsigned gN = grid_for(std::max<int64_t>(n, 1), kT);
     // Histogram and scatter: persistent over the level's tasks.
     const unsigned gR =
         (unsigned)std::min<int64_t>(kPersistBlocks, std::max<int64_t>(1, (n + kRunR - 1) / kRunR));
@@ -1177,19 +1184,21 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
     }
 
     // Leaves renumbered in memory order (depth-first, sub-cells in Morton order).
+    const int64_t nwords = (std::max<int64_t>(n, 1) + 31) / 32;
     hipLaunchKernelGGL(k_fill_i32, dim3(kPersistBlocks), dim3(256), 0, st, W.mark.as<int32_t>(),
-                       std::max<int64_t>(n, 1), -1);
+                       nwords, 0);
     BT_LAUNCH();
-    hipLaunchKernelGGL(k_mark_leaves, dim3(kPersistBlocks), dim3(256), 0, st, t.leaves.as<Leaf>(),
-                       ctl, W.mark.as<int32_t>());
+    hipLaunchKernelGGL(k_mark_bits, dim3(kPersistBlocks), dim3(256), 0, st, t.leaves.as<Leaf>(),
+                       ctl, W.mark.as<uint32_t>());
     BT_LAUNCH();
-    hipLaunchKernelGGL(k_mark_flags, dim3(gN), dim3(256), 0, st, W.mark.as<int32_t>(), n,
-                       W.f.as<int32_t>());
+    hipLaunchKernelGGL(k_popc, dim3(kPersistBlocks), dim3(256), 0, st, W.mark.as<uint32_t>(),
+                       nwords, W.f.as<int32_t>());
     BT_LAUNCH();
-    scan_exclusive_i32(W.f.as<int32_t>(), W.rank.as<int64_t>(), n, t, st);
-    hipLaunchKernelGGL(k_relabel_leaves, dim3(gN), dim3(256), 0, st, W.mark.as<int32_t>(),
-                       W.rank.as<int64_t>(), n, t.leaves.as<Leaf>(), t.ldepth.as<int32_t>(),
-                       t.leaves2.as<Leaf>(), t.ldepth2.as<int32_t>(), W.newid.as<int32_t>());
+    scan_exclusive_i32(W.f.as<int32_t>(), W.rank.as<int64_t>(), nwords, t, st);
+    hipLaunchKernelGGL(k_relabel_leaves, dim3(kPersistBlocks), dim3(256), 0, st,
+                       W.mark.as<uint32_t>(), W.rank.as<int64_t>(), ctl, t.leaves.as<Leaf>(),
+                       t.ldepth.as<int32_t>(), t.leaves2.as<Leaf>(), t.ldepth2.as<int32_t>(),
+                       W.newid.as<int32_t>());
     BT_LAUNCH();
     hipLaunchKernelGGL(k_relabel_ctab, dim3(kPersistBlocks), dim3(256), 0, st, t.ctab.as<int32_t>(),
                        ctl, W.newid.as<int32_t>(), t.sets.as<SetDev>(), t.nsets);
@@ -1199,7 +1208,9 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
     std::swap(t.ldepth.p, t.ldepth2.p);
     std::swap(t.ldepth.bytes, t.ldepth2.bytes);
 
-    hipLaunchKernelGGL(k_leaf_wave, dim3(kPersistBlocks), dim3(kT), 0, st, t.leaves.as<Leaf>(),
+    // Leaf ordering: a wavefront per leaf, with enough wavefronts that each
+    // takes only a few leaves (its steps are chains of dependent loads).
+    hipLaunchKernelGGL(k_leaf_wave, dim3(4 * kPersistBlocks), dim3(kT), 0, st, t.leaves.as<Leaf>(),
                        t.ldepth.as<int32_t>(), ctl, W.P0.as<double4>(), W.P1.as<double4>(),
                        t.pos.as<double4>(), t.lrange.as<int2>());
     BT_LAUNCH();

@@ -153,7 +153,7 @@ void scan_dev_impl(const In* in, int64_t* out, const int32_t* nptr, int64_t ncap
     BT_LAUNCH();
 }
 
-// K arrays of one device length scanned together (three launches for all
+// K arrays of one device length scanned together (two launches for all
 // K): tile sums and tile scans of array q go to tsum[q * (ntiles+1)].
 template <int K>
 struct ScanK {
@@ -182,36 +182,33 @@ __global__ __launch_bounds__(kT) void k_tile_sum_devk(ScanK<K> a, const int32_t*
     }
 }
 
-template <int K>
-__global__ __launch_bounds__(kT) void k_scan_tilesk(int64_t* __restrict__ tsum, int64_t ntiles) {
-    __shared__ int64_t sh[kT / 64 + 1];
-    for (int q = 0; q < K; ++q) {
-        int64_t* ts = tsum + q * (ntiles + 1);
-        int64_t carry = 0;
-        for (int64_t b0 = 0; b0 < ntiles; b0 += kT) {
-            const int64_t k = b0 + threadIdx.x;
-            const int64_t v = k < ntiles ? ts[k] : 0;
-            int64_t tot;
-            const int64_t ex = block_excl_scan<kT>(v, sh, &tot);
-            if (k < ntiles) ts[k] = carry + ex;
-            carry += tot;
-        }
-        if (threadIdx.x == 0) ts[ntiles] = carry;
-    }
-}
-
+// Each workgroup adds the sums of the tiles before its own (a short loop:
+// these scans run over per-cell arrays, a few tiles long), and the one that
+// holds the last element writes the total, so no separate pass scans the
+// tile sums.
 template <int K>
 __global__ __launch_bounds__(kT) void k_tile_scan_devk(ScanK<K> a, const int32_t* __restrict__ nptr,
                                                        const int64_t* __restrict__ tsum,
                                                        int64_t ntiles) {
     __shared__ int64_t sh[kT / 64 + 1];
     const int64_t n = *nptr;
+    const int64_t b = blockIdx.x;
+    if (n <= 0) {
+        if (b == 0 && threadIdx.x == 0) {
+#pragma unroll
+            for (int q = 0; q < K; ++q) a.out[q][0] = 0;
+        }
+        return;
+    }
+    if (b * kTile >= n) return;  // uniform over the workgroup
+    const bool last = (b + 1) * kTile >= n;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
         const int64_t* ts = tsum + q * (ntiles + 1);
-        if (blockIdx.x == 0 && threadIdx.x == 0) a.out[q][n] = ts[ntiles];
-        if ((int64_t)blockIdx.x * kTile >= n) continue;  // uniform over the workgroup
-        const int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+        int64_t pre = 0;
+        for (int64_t j = threadIdx.x; j < b; j += kT) pre += ts[j];
+        pre = block_sum<kT>(pre, sh);
+        const int64_t base = b * kTile + (int64_t)threadIdx.x * kItems;
         int64_t v[kItems];
         int64_t s = 0;
 #pragma unroll
@@ -221,7 +218,8 @@ __global__ __launch_bounds__(kT) void k_tile_scan_devk(ScanK<K> a, const int32_t
             s += v[i];
         }
         int64_t tot;
-        int64_t ex = block_excl_scan<kT>(s, sh, &tot) + ts[blockIdx.x];
+        int64_t ex = block_excl_scan<kT>(s, sh, &tot) + pre;
+        if (last && threadIdx.x == 0) a.out[q][n] = pre + tot;
 #pragma unroll
         for (int i = 0; i < kItems; ++i) {
             const int64_t k = base + i;
@@ -240,8 +238,6 @@ void scank_dev_i64(const ScanK<K>& a, const int32_t* nptr, int64_t ncap, Tree& t
     int64_t* ts = t.scan_tmp.as<int64_t>();
     hipLaunchKernelGGL(k_tile_sum_devk<K>, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
                        ntiles);
-    BT_LAUNCH();
-    hipLaunchKernelGGL(k_scan_tilesk<K>, dim3(1), dim3(kT), 0, st, ts, ntiles);
     BT_LAUNCH();
     hipLaunchKernelGGL(k_tile_scan_devk<K>, dim3((unsigned)ntiles), dim3(kT), 0, st, a, nptr, ts,
                        ntiles);
