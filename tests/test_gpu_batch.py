@@ -243,6 +243,63 @@ def test_batch64_shape_matches_single_trees(prec):
         beg += n
 
 
+def test_batch64_full_size_sampled():
+    """The full Batch64 workload (64 sets, 13.5 M particles) in the form the
+    benchmark times: tuned parameters per set, FP32 filter, the captured
+    graph replayed.  Every row is checked for order and range on the
+    device, replays equal the first run, and sampled rows of every set
+    (random ones plus the largest-h query) equal the oracle's."""
+    import torch
+    from paper_1910_02639_amd import autotune, btree
+    sets = W.batch(64, 0)
+    sizes = [len(s[0]) for s in sets]
+    n = int(sum(sizes))
+    log("Batch64 full", n)
+    dx, dy, dz, dh = to_dev(*_concat(sets))
+    offs = np.zeros(len(sizes) + 1, dtype=np.int64)
+    np.cumsum(sizes, out=offs[1:])
+    tuner = autotune.Tuner(autotune.CACHE)
+    prm = [tuner.params_for(dx[offs[k]:offs[k + 1]], dy[offs[k]:offs[k + 1]],
+                            dz[offs[k]:offs[k + 1]], dh[offs[k]:offs[k + 1]], "fp32")
+           for k in range(len(sizes))]
+    with btree.Batch(sizes, prm, precision="fp32") as B:
+        c0, o0, nb0, totals = B.find(dx, dy, dz, dh)
+        total = int(totals.sum())
+        counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
+        offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+        nbrs = torch.empty(total, dtype=torch.int32, device="cuda:0")
+        for rep in range(2):
+            nbrs.fill_(-1)
+            t2, tot2 = B.run(dx, dy, dz, dh, counts, offsets, nbrs)
+            torch.cuda.synchronize()
+            assert tot2 == total and list(t2) == list(totals)
+            assert torch.equal(counts, c0) and torch.equal(offsets, o0)
+            assert torch.equal(nbrs, nb0), "replay %d differs from the first run" % rep
+    log("Batch64 total", total)
+    # CSR shape, row order and index range, on the device.
+    o = o0
+    assert int(o[0]) == 0 and int(o[-1]) == total
+    assert torch.equal(o[1:] - o[:-1], c0.to(torch.int64))
+    start = torch.zeros(total, dtype=torch.bool, device="cuda:0")
+    start[o[:-1][c0 > 0]] = True
+    assert not bool(((nb0[1:] <= nb0[:-1]) & ~start[1:]).any()), "a row is not ascending"
+    size_of = torch.repeat_interleave(torch.tensor(sizes, device="cuda:0"),
+                                      torch.tensor(sizes, device="cuda:0"))
+    lim = torch.repeat_interleave(size_of, c0.to(torch.int64))
+    assert bool((nb0 >= 0).all()) and bool((nb0 < lim).all())
+    del start, size_of, lim
+    c, oh = c0.cpu().numpy(), o0.cpu().numpy()
+    rng = np.random.default_rng(11)
+    for k, (xs, ys, zs, hs) in enumerate(sets):
+        rows = np.unique(np.concatenate([rng.integers(0, sizes[k], 4), [int(np.argmax(hs))]]))
+        for i in rows:
+            g = int(offs[k]) + int(i)
+            got = nb0[int(oh[g]):int(oh[g + 1])].cpu().numpy()
+            assert np.array_equal(got, oracle.row(xs, ys, zs, hs, int(i))), \
+                "set %d row %d" % (k, int(i))
+            assert c[g] == len(got)
+
+
 def test_tuner_picks_a_candidate_and_results_do_not_depend_on_it():
     """btree_tune times every candidate (device time of the recorded graph)
     and returns the fastest; lists with any candidate equal the oracle's."""
