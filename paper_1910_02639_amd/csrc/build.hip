@@ -858,85 +858,120 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
     __shared__ int32_t val[kSortMax];
     __shared__ int32_t ord[kSortMax];
     __shared__ int32_t red[2][kT / 64];
+    __shared__ int32_t s_big[kT];
+    __shared__ int s_nbig;
     const int64_t nl = ctl->n_leaves;
-    for (int64_t li = blockIdx.x; li < nl; li += gridDim.x) {
-        const Leaf L = leaves[li];
-        if (L.cnt <= kWaveSort) continue;  // done by k_leaf_wave
-        const double4* src = (ldepth[li] & 1) ? P1 : P0;
-        const SetDev& S = sets[set_of(sets, nsets, L.beg)];
+    // Each workgroup lists the large leaves of a range of kT leaves (one
+    // load per thread), then orders them one after the other.
+    for (int64_t base = (int64_t)blockIdx.x * kT; base < nl; base += (int64_t)gridDim.x * kT) {
+        if (threadIdx.x == 0) s_nbig = 0;
+        __syncthreads();
         {
-            int mn = 0x7fffffff, mx = -1;
-            for (int k = threadIdx.x; k < L.cnt; k += kT) {
-                const int v = (int)src[L.beg + k].w;
-                mn = min(mn, v);
-                mx = max(mx, v);
-            }
-#pragma unroll
-            for (int d = 32; d > 0; d >>= 1) {
-                mn = min(mn, __shfl_xor(mn, d, 64));
-                mx = max(mx, __shfl_xor(mx, d, 64));
-            }
-            if (lane_id() == 0) { red[0][threadIdx.x >> 6] = mn; red[1][threadIdx.x >> 6] = mx; }
-            __syncthreads();
-            if (threadIdx.x == 0) {
-                for (int k = 1; k < kT / 64; ++k) { mn = min(mn, red[0][k]); mx = max(mx, red[1][k]); }
-                lrange[li] = make_int2(mn, mx);
-            }
-        }
-        // A leaf too large to sort here keeps the order of the Morton pre-sort.
-        if (L.cnt > kSortMax) {
-            for (int k = threadIdx.x; k < L.cnt; k += kT) pos[L.beg + k] = src[L.beg + k];
-            __syncthreads();
-            continue;
-        }
-        const double sx = (double)(1 << 21) / fmax(S.box[3] - S.box[0], 1e-300);
-        const double sy = (double)(1 << 21) / fmax(S.box[4] - S.box[1], 1e-300);
-        const double sz = (double)(1 << 21) / fmax(S.box[5] - S.box[2], 1e-300);
-        int P = 1;
-        while (P < L.cnt) P <<= 1;
-        for (int k = threadIdx.x; k < P; k += kT) {
-            if (k < L.cnt) {
-                const double4 q = src[L.beg + k];
-                key[k] = leaf_key(q, S, sx, sy, sz);
-                val[k] = (int32_t)q.w;
-            } else {
-                key[k] = ~0ull;
-                val[k] = 0x7fffffff;
-            }
-            ord[k] = k;
+            const int64_t l = base + threadIdx.x;
+            if (l < nl && leaves[l].cnt > kWaveSort) s_big[atomicAdd(&s_nbig, 1)] = (int32_t)l;
         }
         __syncthreads();
-        for (int kk = 2; kk <= P; kk <<= 1) {
-            for (int j = kk >> 1; j > 0; j >>= 1) {
-                for (int a = threadIdx.x; a < P; a += kT) {
-                    const int c = a ^ j;
-                    if (c > a) {
-                        const bool up = (a & kk) == 0;
-                        const bool gt = key[a] > key[c] || (key[a] == key[c] && val[a] > val[c]);
-                        if (gt == up) {
-                            const uint64_t tk = key[a]; key[a] = key[c]; key[c] = tk;
-                            const int32_t tv = val[a]; val[a] = val[c]; val[c] = tv;
-                            const int32_t to = ord[a]; ord[a] = ord[c]; ord[c] = to;
+        const int nbig = s_nbig;
+        for (int bi = 0; bi < nbig; ++bi) {
+            const int64_t li = s_big[bi];
+            const Leaf L = leaves[li];
+            const double4* src = (ldepth[li] & 1) ? P1 : P0;
+            const SetDev& S = sets[set_of(sets, nsets, L.beg)];
+            {
+                int mn = 0x7fffffff, mx = -1;
+                for (int k = threadIdx.x; k < L.cnt; k += kT) {
+                    const int v = (int)src[L.beg + k].w;
+                    mn = min(mn, v);
+                    mx = max(mx, v);
+                }
+#pragma unroll
+                for (int d = 32; d > 0; d >>= 1) {
+                    mn = min(mn, __shfl_xor(mn, d, 64));
+                    mx = max(mx, __shfl_xor(mx, d, 64));
+                }
+                if (lane_id() == 0) { red[0][threadIdx.x >> 6] = mn; red[1][threadIdx.x >> 6] = mx; }
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    for (int k = 1; k < kT / 64; ++k) { mn = min(mn, red[0][k]); mx = max(mx, red[1][k]); }
+                    lrange[li] = make_int2(mn, mx);
+                }
+            }
+            // A leaf too large to sort here keeps the order of the Morton pre-sort.
+            if (L.cnt > kSortMax) {
+                for (int k = threadIdx.x; k < L.cnt; k += kT) pos[L.beg + k] = src[L.beg + k];
+                __syncthreads();
+                continue;
+            }
+            const double sx = (double)(1 << 21) / fmax(S.box[3] - S.box[0], 1e-300);
+            const double sy = (double)(1 << 21) / fmax(S.box[4] - S.box[1], 1e-300);
+            const double sz = (double)(1 << 21) / fmax(S.box[5] - S.box[2], 1e-300);
+            int P = 1;
+            while (P < L.cnt) P <<= 1;
+            for (int k = threadIdx.x; k < P; k += kT) {
+                if (k < L.cnt) {
+                    const double4 q = src[L.beg + k];
+                    key[k] = leaf_key(q, S, sx, sy, sz);
+                    val[k] = (int32_t)q.w;
+                } else {
+                    key[k] = ~0ull;
+                    val[k] = 0x7fffffff;
+                }
+                ord[k] = k;
+            }
+            __syncthreads();
+            for (int kk = 2; kk <= P; kk <<= 1) {
+                for (int j = kk >> 1; j > 0; j >>= 1) {
+                    for (int a = threadIdx.x; a < P; a += kT) {
+                        const int c = a ^ j;
+                        if (c > a) {
+                            const bool up = (a & kk) == 0;
+                            const bool gt = key[a] > key[c] || (key[a] == key[c] && val[a] > val[c]);
+                            if (gt == up) {
+                                const uint64_t tk = key[a]; key[a] = key[c]; key[c] = tk;
+                                const int32_t tv = val[a]; val[a] = val[c]; val[c] = tv;
+                                const int32_t to = ord[a]; ord[a] = ord[c]; ord[c] = to;
+                            }
                         }
                     }
+                    __syncthreads();
                 }
-                __syncthreads();
             }
+            for (int k = threadIdx.x; k < L.cnt; k += kT) pos[L.beg + k] = src[L.beg + ord[k]];
+            __syncthreads();
         }
-        for (int k = threadIdx.x; k < L.cnt; k += kT) pos[L.beg + k] = src[L.beg + ord[k]];
-        __syncthreads();
+        __syncthreads();  // s_nbig is reset for the next range
     }
 }
 
 __global__ void k_leaf_stats(const Leaf* __restrict__ leaves, const int32_t* __restrict__ ldepth,
                              const SetDev* __restrict__ sets, int nsets, Ctl* __restrict__ ctl) {
     const int64_t nl = ctl->n_leaves;
-    for (int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; l < nl;
-         l += (int64_t)gridDim.x * blockDim.x) {
-        const Leaf L = leaves[l];
-        atomicMax(&ctl->depth, ldepth[l]);
-        atomicMax(&ctl->max_leaf, L.cnt);
-        if (L.cnt > sets[set_of(sets, nsets, L.beg)].s) atomicAdd(&ctl->oversized, 1);
+    // Reduced over the wavefront first (the loop bound is uniform over the
+    // workgroup, so every lane takes part).
+    for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < nl;
+         b0 += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t l = b0 + threadIdx.x;
+        int d = 0, c = 0, o = 0;
+        if (l < nl) {
+            const Leaf L = leaves[l];
+            d = ldepth[l];
+            c = L.cnt;
+            o = L.cnt > sets[set_of(sets, nsets, L.beg)].s ? 1 : 0;
+        }
+#pragma unroll
+        for (int k = 32; k > 0; k >>= 1) {
+            d = max(d, __shfl_xor(d, k, 64));
+            c = max(c, __shfl_xor(c, k, 64));
+            o += __shfl_xor(o, k, 64);
+        }
+        // Atomics on one address are serialised, so a maximum is only sent
+        // when it beats the value read (which can only be lower than the
+        // current one: both fields only grow).
+        if ((threadIdx.x & 63) == 0) {
+            if (d > ctl->depth) atomicMax(&ctl->depth, d);
+            if (c > ctl->max_leaf) atomicMax(&ctl->max_leaf, c);
+            if (o > 0) atomicAdd(&ctl->oversized, o);
+        }
     }
 }
 
