@@ -945,9 +945,10 @@ __global__ __launch_bounds__(kT) void k_leaf_final(const Leaf* __restrict__ leav
 
 __global__ void k_leaf_stats(const Leaf* __restrict__ leaves, const int32_t* __restrict__ ldepth,
                              const SetDev* __restrict__ sets, int nsets, Ctl* __restrict__ ctl) {
+    __shared__ int red[3][4];
     const int64_t nl = ctl->n_leaves;
-    // Reduced over the wavefront first (the loop bound is uniform over the
-    // workgroup, so every lane takes part).
+    // Reduced over the workgroup first (the loop bound is uniform over it,
+    // so every lane takes part): atomics on one address are serialised.
     for (int64_t b0 = (int64_t)blockIdx.x * blockDim.x; b0 < nl;
          b0 += (int64_t)gridDim.x * blockDim.x) {
         const int64_t l = b0 + threadIdx.x;
@@ -964,14 +965,24 @@ __global__ void k_leaf_stats(const Leaf* __restrict__ leaves, const int32_t* __r
             c = max(c, __shfl_xor(c, k, 64));
             o += __shfl_xor(o, k, 64);
         }
-        // Atomics on one address are serialised, so a maximum is only sent
-        // when it beats the value read (which can only be lower than the
-        // current one: both fields only grow).
+        const int w = threadIdx.x >> 6;
         if ((threadIdx.x & 63) == 0) {
+            red[0][w] = d;
+            red[1][w] = c;
+            red[2][w] = o;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int k = 1; k < (int)(blockDim.x >> 6); ++k) {
+                d = max(d, red[0][k]);
+                c = max(c, red[1][k]);
+                o += red[2][k];
+            }
             if (d > ctl->depth) atomicMax(&ctl->depth, d);
             if (c > ctl->max_leaf) atomicMax(&ctl->max_leaf, c);
             if (o > 0) atomicAdd(&ctl->oversized, o);
         }
+        __syncthreads();
     }
 }
 

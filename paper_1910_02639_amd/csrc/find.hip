@@ -1170,6 +1170,14 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
             to_brute(unit, pos, soff, ctl, brute, bcnt, stats);
             continue;
         }
+        if (LEVEL == 1 && src.pad < kHuge && src.pad > kCMaxSplit<F32>) {
+            // The main sweep counted the candidates inside this item's box
+            // (the same box here): more than this budget too, so the item
+            // goes on to the parts without being staged again.
+            if (threadIdx.x == 0)
+                next[atomicAdd(&ctl->nsplit2, 1u)] = Chunk{unit.beg, unit.cnt, unit.set, src.pad};
+            continue;
+        }
         // Level 1 takes the item whole: its walk list, if whole, still holds.
         const int ci = LEVEL == 1 ? split_ci[u] : -1;
         const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2)>(
