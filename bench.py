@@ -91,6 +91,21 @@ def roofline(kernel_ms, tests, ops, kernel, workload):
             "algorithmic_ops_per_launch": tests * ops}
 
 
+def hbm_measured(ph, workload):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+    profiles/traffic.json) over the kernel's time in this run, against the
+    8 TB/s peak.  The placement time is the placement phase as timed (in the
+    batched graph it also holds the exhaustive fill)."""
+    out = {}
+    for key, name in (("sweep_kernel", "k_sweep"), ("place_kernel", "k_place")):
+        t = load_traffic(key, workload)
+        if t is None or ph.get(key, 0.0) <= 0.0:
+            continue
+        gbs = t / (ph[key] * 1e-3) / 1e9
+        out[name] = {"hbm_bytes": t, "ms": ph[key], "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    return out or None
+
+
 def search_hbm(n, total, search_ms):
     # Compulsory HBM bytes of the whole search (both passes), per particle:
     # coordinates 24 B + h 8 B + count 4 B + offset 8 B, plus 4 B per entry.
@@ -155,7 +170,8 @@ def bench_single(name, precision, steps, warmup, compare, tuner, bucket=0):
                     "leaves": st["n_leaves"], "b_hist": st["b_hist"]},
            "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], ops,
                                 "k_sweep<%s>" % precision, name),
-           "search_hbm": search_hbm(n, total, ph["pass1"] + ph["pass2"])}
+           "search_hbm": search_hbm(n, total, ph["pass1"] + ph["pass2"]),
+           "hbm_measured": hbm_measured(ph, name) if precision == "fp32" else None}
     if compare and precision == "fp32":
         log("fp64 plain", name)
         p64 = tuner.params_for(dx, dy, dz, dh, "fp64") if not bucket else prm
@@ -266,6 +282,7 @@ def bench_batch(a, tuner):
         "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], OPS_PER_TEST_F32,
                              "k_sweep<fp32>", "Batch64"),
         "search_hbm": search_hbm(n, total, ph["pass1"] + ph["pass2"]),
+        "hbm_measured": hbm_measured(ph, "Batch64"),
     }
     if not a.no_compare:
         k2 = max(2, min(a.steps, 5))
