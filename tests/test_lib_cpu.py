@@ -122,6 +122,26 @@ def test_product_never_imports_oracle():
             assert "_oracle.so" not in s, f
 
 
+def test_missing_library_fails_loudly(tmp_path):
+    """Without the built HIP library every entry of the binding raises: there
+    is no other path to take."""
+    import subprocess
+    import sys
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1910_02639_amd import btree\n"
+        "btree.LIB_PATH = %r\n"
+        "try:\n"
+        "    btree.lib()\n"
+        "except RuntimeError as e:\n"
+        "    print('raised:', e)\n"
+        "    sys.exit(0)\n"
+        "sys.exit(3)\n" % (ROOT, str(tmp_path / "absent" / "libbtree.so")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "not built" in r.stdout
+
+
 def _batch_create(L, nsets, offs, prm=None, out=True):
     import numpy as np
     h = ctypes.c_void_p()
