@@ -293,6 +293,7 @@ struct Tree {
     DBuf stripes;  // uint64 cursors: kStripes for the scratch, then kStripes for the walk lists
     DBuf hs;       // double per particle: h in tree order (filled by each search)
     DBuf whdr;     // int4 per work item: walk result header
+    DBuf ibox;     // per work item: box E and the FP32 filter's item-wide bounds (64 bytes)
     DBuf wl;       // int2 pool: candidate leaves (first particle, count) of every item
     Work ws;
     Timer timer;

@@ -272,6 +272,32 @@ __device__ __forceinline__ void item_box(bool qv, const double4& qp, double R, d
     }
 }
 
+// The item-wide part of the FP32 filter's set-up: the norm bound |S| of the
+// per-axis staging bounds and the largest radius (derivation at the top of
+// the file).  The walk computes it with the box and keeps both per item, so
+// the main sweep's four wavefronts need not reduce them again.
+struct ItemBox {
+    double lo[3], hi[3];
+    double sn, rmax;
+};
+
+__device__ __forceinline__ void item_bounds(bool qv, const double4& qp, double R,
+                                            const double elo[3], const double ehi[3],
+                                            double& sn, double& rmax) {
+    const double up = 1.0 + 0x1p-50;
+    const double c3[3] = {elo[0] + (ehi[0] - elo[0]) * 0.5, elo[1] + (ehi[1] - elo[1]) * 0.5,
+                          elo[2] + (ehi[2] - elo[2]) * 0.5};
+    const double q3[3] = {qp.x, qp.y, qp.z};
+    double S[3];
+    for (int l = 0; l < 3; ++l) {
+        const double mb = fmax(c3[l] - elo[l], ehi[l] - c3[l]) * up;
+        const double ma = wave_max(qv ? fabs(q3[l] - c3[l]) : 0.0) * up;
+        S[l] = (ma + mb) * up;
+    }
+    sn = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) * up;
+    rmax = wave_max(R);
+}
+
 // Stripe of a pool (scratch, walk lists) that a unit starting at sorted position `beg`
 // allocates from: a function of the unit alone, so that a search repeated
 // over the same data asks each stripe for the same amount.
@@ -301,7 +327,7 @@ __global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
                                              double* __restrict__ hs,
                                              int4* __restrict__ whdr, int2* __restrict__ wl,
                                              int64_t wl_cap, unsigned long long* __restrict__ wcur,
-                                             Ctl* __restrict__ ctl) {
+                                             ItemBox* __restrict__ ibox, Ctl* __restrict__ ctl) {
     __shared__ int32_t s_front[2][kFMax];
     __shared__ int32_t s_pref[kFMax + 1];
     __shared__ int64_t s_tab[kFMax];      // child-table offset of frontier cell j
@@ -324,6 +350,16 @@ __global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
     const double R = 2.0 * hv;
     double elo[3], ehi[3];
     item_box(qv, qp, R, elo, ehi);
+    {
+        double sn, rmax;
+        item_bounds(qv, qp, R, elo, ehi, sn, rmax);
+        // Eight doubles, one per lane (the values are uniform).
+        const double f[8] = {elo[0], elo[1], elo[2], ehi[0], ehi[1], ehi[2], sn, rmax};
+        double v = f[0];
+#pragma unroll
+        for (int k = 1; k < 8; ++k) v = lane == k ? f[k] : v;
+        if (lane < 8) reinterpret_cast<double*>(ibox + ci)[lane] = v;
+    }
     const int32_t root_code = __builtin_amdgcn_readfirstlane(sets[ch.set].root);
 
     int nleaf = 0, nf = 0, cur = 0;
@@ -463,6 +499,7 @@ template <bool F32, int WALK, int CMAX = kCMax, int LMAX = kLMax, bool SMALL = f
 __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                                           const int4* __restrict__ whdr,
                                           const int2* __restrict__ wl,
+                                          const ItemBox* __restrict__ ibox,
                                           const double4* __restrict__ pos,
                                            const double4* __restrict__ orig,
                                            const Node* __restrict__ nodes,
@@ -516,9 +553,21 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     const int qidx = (int)qp.w;
     const double R = qv ? 2.0 * h[ch.beg + lane] : 0.0;
 
-    // Box E of the item.
-    double elo[3], ehi[3];
-    item_box(qv, qp, R, elo, ehi);
+    // Box E of the item and the filter's item-wide bounds: from the walk
+    // kernel's record when the item has one, else reduced here.
+    double elo[3], ehi[3], sn = 0.0, rmax = 0.0;
+    if (WALK == 1) {
+        const ItemBox ib = ibox[ci];
+        for (int l = 0; l < 3; ++l) {
+            elo[l] = ib.lo[l];
+            ehi[l] = ib.hi[l];
+        }
+        sn = ib.sn;
+        rmax = ib.rmax;
+    } else {
+        item_box(qv, qp, R, elo, ehi);
+        if (F32) item_bounds(qv, qp, R, elo, ehi, sn, rmax);
+    }
 
     // FP32 filter set-up (derivation at the top of the file).
     float ax = 0.f, ay = 0.f, az = 0.f, tlo = -1.f, thi = -1.f;
@@ -528,17 +577,6 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         cx = elo[0] + (ehi[0] - elo[0]) * 0.5;
         cy = elo[1] + (ehi[1] - elo[1]) * 0.5;
         cz = elo[2] + (ehi[2] - elo[2]) * 0.5;
-        const double up = 1.0 + 0x1p-50;
-        const double c3[3] = {cx, cy, cz};
-        const double q3[3] = {qp.x, qp.y, qp.z};
-        double S[3];
-        for (int l = 0; l < 3; ++l) {
-            const double mb = fmax(c3[l] - elo[l], ehi[l] - c3[l]) * up;
-            const double ma = wave_max(qv ? fabs(q3[l] - c3[l]) : 0.0) * up;
-            S[l] = (ma + mb) * up;
-        }
-        const double sn = sqrt(S[0] * S[0] + S[1] * S[1] + S[2] * S[2]) * up;
-        const double rmax = wave_max(R);
         // Every square, product and threshold below stays under 2^128.
         unsafe = !(sn < 0x1p60 && rmax < 0x1p60);
         const double u = 0x1p-24;
@@ -1078,6 +1116,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                int32_t* __restrict__ split_ci,
                                                const int4* __restrict__ whdr,
                                                const int2* __restrict__ wl,
+                                               const ItemBox* __restrict__ ibox,
                                                Stats* __restrict__ stats) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     const int nch = ctl->n_chunks;
@@ -1086,7 +1125,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         atomicOr(&ctl->overflow, kOvfChunks);
     if (ci >= nch) return;
     const Chunk ch = chunks[ci];
-    const int C = sweep_item<F32, 1>(ci, ch, whdr, wl, pos, orig, nodes, ctab, leaves, lrange,
+    const int C = sweep_item<F32, 1>(ci, ch, whdr, wl, ibox, pos, orig, nodes, ctab, leaves, lrange,
                                         sets, h, counts, soff, scratch, scap, scur,
                                         stripe_of(ch.beg), ctl, stats);
     if (C && threadIdx.x == 0) {
@@ -1181,8 +1220,8 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         // Level 1 takes the item whole: its walk list, if whole, still holds.
         const int ci = LEVEL == 1 ? split_ci[u] : -1;
         const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2)>(
-            ci, unit, whdr, wl, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
-            scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
+            ci, unit, whdr, wl, nullptr, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts,
+            soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
         if (!C) continue;
         __syncthreads();
         if (LEVEL == 3 || (nset <= kDenseSet && C != kNoCount && 4 * (int64_t)C > nset)) {
@@ -1546,7 +1585,8 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipS
                        t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.split_ci.as<int32_t>(),
-                       t.whdr.as<int4>(), t.wl.as<int2>(), t.stats.as<Stats>());
+                       t.whdr.as<int4>(), t.wl.as<int2>(), t.ibox.as<ItemBox>(),
+                       t.stats.as<Stats>());
     BT_LAUNCH();
 }
 
@@ -1584,6 +1624,7 @@ void find_reserve(Tree& t, int64_t entries) {
     // item that does not fit the pool is searched by the split path).
     const int64_t items = std::max<int64_t>(std::max(t.n_chunks, t.chunk_cap), 1);
     t.whdr.reserve(sizeof(int4) * items);
+    t.ibox.reserve(sizeof(ItemBox) * items);
     const int64_t wl_want = std::max(kWalkPerItem * items, t.wl_need);
     if (t.wl_cap < wl_want) {
         t.wl.release();
@@ -1616,7 +1657,8 @@ void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st) {
                        t.lrange.as<int2>(), t.sets.as<SetDev>(), h, t.hs.as<double>(),
                        t.whdr.as<int4>(),
                        t.wl.as<int2>(), t.wl_cap,
-                       t.stripes.as<unsigned long long>() + kStripes * kStripeStride, t.ctl.as<Ctl>());
+                       t.stripes.as<unsigned long long>() + kStripes * kStripeStride,
+                       t.ibox.as<ItemBox>(), t.ctl.as<Ctl>());
     BT_LAUNCH();
 }
 
