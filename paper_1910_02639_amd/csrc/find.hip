@@ -686,7 +686,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
             const uint64_t m = __ballot(in);
             int b = 0;
             if (lane == 0 && m) b = atomicAdd(&s_C, (int)__popcll(m));
-            b = __shfl(b, 0, 64);
+            b = __builtin_amdgcn_readfirstlane(b);  // every lane is active: lane 0's value
             if (in) {
                 atomicAdd(&s_bcnt[bucket((int)P.w)], 1);
                 const int slot = b + lanes_below(m);
@@ -1003,7 +1003,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         if (!qv) c = 0;
         const int inc = wave_incl_scan(c);
         s_qoff[lane] = inc - c;
-        const int total = __shfl(inc, 63, 64);
+        const int total = __builtin_amdgcn_readlane(inc, 63);
         if (lane == 0) {
             s_total = total;
             s_base = atomicAdd(&scur[stripe * kStripeStride], (unsigned long long)total);
