@@ -1048,8 +1048,13 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     // memory for coalesced stores was slower: the extra barriers put every
     // wavefront's extraction on the item's critical path.)
     if (qv) {
-        int64_t at = base + s_qoff[lane];
-        for (int k = 0; k < w; ++k) at += s_cnt[k][lane];
+        int64_t at0 = base + s_qoff[lane];
+        for (int k = 0; k < w; ++k) at0 += s_cnt[k][lane];
+        // Positions from here on are relative to the lane's first entry;
+        // `head` entries go one by one up to the first 16-byte boundary.
+        int32_t* const row = scratch + at0;
+        int head = (int)((4 - (at0 & 3)) & 3);
+        int at = 0;
         int32_t b0 = 0, b1 = 0, b2 = 0, b3 = 0;
         int nb = 0;
 #pragma unroll
@@ -1062,8 +1067,9 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                     const int j = __clz(word);
                     word &= ~(0x80000000u >> j);
                     const int32_t v = Ent<F32>::key(cand(kb + j)) - sbeg;
-                    if (nb == 0 && (at & 3)) {
-                        scratch[at++] = v;  // up to the first aligned position
+                    if (head > 0) {
+                        row[at++] = v;
+                        --head;
                         continue;
                     }
                     b0 = b1;
@@ -1071,7 +1077,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                     b2 = b3;
                     b3 = v;
                     if (++nb == 4) {
-                        *reinterpret_cast<int4*>(scratch + at) = make_int4(b0, b1, b2, b3);
+                        *reinterpret_cast<int4*>(row + at) = make_int4(b0, b1, b2, b3);
                         at += 4;
                         nb = 0;
                     }
@@ -1080,14 +1086,14 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         }
         // The last one to three entries sit at the top of the buffer.
         if (nb == 3) {
-            scratch[at] = b1;
-            scratch[at + 1] = b2;
-            scratch[at + 2] = b3;
+            row[at] = b1;
+            row[at + 1] = b2;
+            row[at + 2] = b3;
         } else if (nb == 2) {
-            scratch[at] = b2;
-            scratch[at + 1] = b3;
+            row[at] = b2;
+            row[at + 1] = b3;
         } else if (nb == 1) {
-            scratch[at] = b3;
+            row[at] = b3;
         }
     }
     return 0;
