@@ -366,8 +366,16 @@ __global__ __launch_bounds__(kT) void k_select(Node* __restrict__ nodes,
                                                int64_t* __restrict__ selofs,
                                                Stats* __restrict__ stats) {
     __shared__ int64_t sh[kT / 64 + 1];
+    // Statistics summed per workgroup and sent once at the end: atomics on
+    // one address are serialised, and a level can hold thousands of cells.
+    __shared__ unsigned s_bh[65];
+    __shared__ unsigned s_rounds;
     if (!ctl->level_ok) return;
     const int64_t nb = ctl->cur_nb, m = ctl->lvm;
+    if ((int64_t)blockIdx.x >= m) return;  // uniform: no cell for this workgroup
+    for (int k = threadIdx.x; k < 65; k += kT) s_bh[k] = 0;
+    if (threadIdx.x == 0) s_rounds = 0;
+    __syncthreads();
     for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
         const int64_t node = nb + i;
         const SetDev& S = sets[nodes[node].set];
@@ -389,10 +397,14 @@ __global__ __launch_bounds__(kT) void k_select(Node* __restrict__ nodes,
             bsel[i] = bb;
             selofs[i] = off;
             nodes[node].b = bb;
-            atomicAdd(&stats->rounds, (unsigned long long)rounds);
-            atomicAdd(&stats->b_hist[bb < 64 ? bb : 64], 1ull);
+            s_rounds += (unsigned)rounds;
+            s_bh[bb < 64 ? bb : 64] += 1u;
         }
     }
+    __syncthreads();
+    for (int k = threadIdx.x; k < 65; k += kT)
+        if (s_bh[k]) atomicAdd(&stats->b_hist[k], (unsigned long long)s_bh[k]);
+    if (threadIdx.x == 0 && s_rounds) atomicAdd(&stats->rounds, (unsigned long long)s_rounds);
 }
 
 constexpr int kChildItems = 4;
