@@ -1170,14 +1170,18 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
                        t.nodes.as<Node>(), t.leaves.as<Leaf>(), t.ldepth.as<int32_t>(), ctl);
     BT_LAUNCH();
     if (t.ntiles > 0) {
+        // The pre-sort only gives the level kernels locality, so 24 key bits
+        // (three radix passes) do: the set id above a Morton code on a grid of
+        // 2^abits cells per axis of the set's root box.
         const int setbits = ceil_log2(t.nsets);
-        const int abits = std::min(10, (32 - setbits) / 3);
+        const int abits = std::max(0, std::min(10, (24 - setbits) / 3));
+        const int kbits = ((setbits + 3 * abits + 7) / 8) * 8;
         hipLaunchKernelGGL(k_morton, dim3(nt), dim3(kT), 0, st, t.orig.as<double4>(),
                            W.tiles.as<Tile>(), t.sets.as<SetDev>(), abits, W.mk0.as<uint32_t>(),
                            W.mv0.as<int32_t>());
         BT_LAUNCH();
         radix_sort_pairs(W.mk0.as<uint32_t>(), W.mv0.as<int32_t>(), W.mk1.as<uint32_t>(),
-                         W.mv1.as<int32_t>(), n, 32, t, W.rcnt, W.roff, st);
+                         W.mv1.as<int32_t>(), n, kbits, t, W.rcnt, W.roff, st);
         hipLaunchKernelGGL(k_gather, dim3(nt), dim3(kT), 0, st, t.orig.as<double4>(),
                            W.mv0.as<int32_t>(), W.tiles.as<Tile>(), W.P0.as<double4>());
         BT_LAUNCH();

@@ -347,6 +347,9 @@ __global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
         hv = h[(int)qp.w];
         hs[ch.beg + lane] = hv;
     }
+    // h must be finite and >= 0 (the work items cover every particle once);
+    // the later kernels write nothing once the flag is up.
+    if (__ballot(qv && !(hv >= 0.0 && isfinite(hv))) && lane == 0) atomicOr(&ctl->data_bad, 2);
     const double R = 2.0 * hv;
     double elo[3], ehi[3];
     item_box(qv, qp, R, elo, ehi);
@@ -556,7 +559,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     // Box E of the item and the filter's item-wide bounds: from the walk
     // kernel's record when the item has one, else reduced here.
     double elo[3], ehi[3], sn = 0.0, rmax = 0.0;
-    if (WALK == 1) {
+    if (WALK == 1 || (WALK == 2 && ci >= 0 && ibox != nullptr)) {
         const ItemBox ib = ibox[ci];
         for (int l = 0; l < 3; ++l) {
             elo[l] = ib.lo[l];
@@ -1181,6 +1184,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
                                                      const int32_t* __restrict__ split_ci,
                                                      const int4* __restrict__ whdr,
                                                      const int2* __restrict__ wl,
+                                                     const ItemBox* __restrict__ ibox,
                                                      const double4* __restrict__ pos,
                                                      const double4* __restrict__ orig,
                                                      const Node* __restrict__ nodes,
@@ -1226,8 +1230,8 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         // Level 1 takes the item whole: its walk list, if whole, still holds.
         const int ci = LEVEL == 1 ? split_ci[u] : -1;
         const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2)>(
-            ci, unit, whdr, wl, nullptr, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts,
-            soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
+            ci, unit, whdr, wl, LEVEL == 1 ? ibox : nullptr, pos, orig, nodes, ctab, leaves, lrange,
+            sets, h, counts, soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
         if (!C) continue;
         __syncthreads();
         if (LEVEL == 3 || (nset <= kDenseSet && C != kNoCount && 4 * (int64_t)C > nset)) {
@@ -1562,16 +1566,6 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
     }
 }
 
-__global__ void k_check_h(const double* __restrict__ h, int64_t n, Ctl* __restrict__ ctl) {
-    bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        double v = h[i];
-        bad |= !(v >= 0.0 && isfinite(v));
-    }
-    if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->data_bad, 2);
-}
-
 // Lists per set: totals[k] = offsets[end of set k] - offsets[start of set k].
 __global__ void k_set_totals(const int64_t* __restrict__ offsets, const SetDev* __restrict__ sets,
                              int nsets, int64_t* __restrict__ totals) {
@@ -1601,7 +1595,7 @@ void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* 
                         hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_split<F32, LEVEL>), dim3(kSplitGrid), dim3(kWG), 0, st, in, next,
                        t.split_ci.as<int32_t>(), t.whdr.as<int4>(), t.wl.as<int2>(),
-                       t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
+                       t.ibox.as<ItemBox>(), t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
@@ -1650,9 +1644,6 @@ void find_begin(Tree& t, const double* h, hipStream_t st) {
     hipLaunchKernelGGL(k_find_reset, dim3(1), dim3(2 * kStripes), 0, st, t.ctl.as<Ctl>(),
                        t.stats.as<Stats>(), t.stripes.as<unsigned long long>(),
                        t.bset.as<int32_t>(), (int)t.nsets);
-    BT_LAUNCH();
-    hipLaunchKernelGGL(k_check_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 2048)), dim3(256), 0,
-                       st, h, t.n, t.ctl.as<Ctl>());
     BT_LAUNCH();
 }
 
