@@ -1595,8 +1595,8 @@ void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* 
                         hipStream_t st) {
     hipLaunchKernelGGL((k_sweep_split<F32, LEVEL>), dim3(kSplitGrid), dim3(kWG), 0, st, in, next,
                        t.split_ci.as<int32_t>(), t.whdr.as<int4>(), t.wl.as<int2>(),
-                       t.ibox.as<ItemBox>(), t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
-                       t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
+                       t.ibox.as<ItemBox>(), t.pos.as<double4>(), t.orig.as<double4>(),
+                       t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.blist.as<Chunk>(), t.bset.as<int32_t>(),
