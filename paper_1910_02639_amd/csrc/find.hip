@@ -10,7 +10,9 @@
 //     max_i fl(x_i + 2h_i)]; walk (Algorithm 2 with Eq. 5 applied to E),
 //     breadth first: each internal cell's sub-cell range on every axis is
 //     [f(E_lo), f(E_hi)] with the build's own Eq. 2 function f.  The
-//     candidate leaves go to a pool in global memory.
+//     candidate leaves go to a pool in global memory, E and the FP32
+//     filter's item-wide bounds to a record per item; the walk also checks
+//     that h is finite and >= 0.
 //  2. k_sweep, one workgroup of 4 wavefronts per item (lane q of every
 //     wavefront holds query q): the particles of the candidate leaves that
 //     lie inside E are staged into LDS (every true neighbour of every query
