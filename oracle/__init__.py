@@ -9,9 +9,14 @@ The arithmetic lives in ``oracle.c`` (plain C, FP64, no FMA contraction):
 * ``lists`` / ``counts`` / ``row``: the definition of FindNeighbors' result
   (Section 3.2, Algorithm 2): for each query i, every j with
   ``((dx*dx + dy*dy) + dz*dz) < (2*h_i)*(2*h_i)``, ascending in j.
+* ``cell_lists`` / ``cell_check``: the same lists by an exact multi-resolution
+  cell list (every tested pair through the same predicate), for sets too
+  large for the brute force; ``cell_check`` compares lists produced
+  elsewhere row by row.  Pinned to the brute force byte for byte.
 * ``build_tree``: Algorithm 1 (BuildTree) with Eqs. 1-4, as a recursion in
   the paper's order, reporting the tree shape and each leaf's members in a
-  canonical depth-first order.
+  canonical depth-first order; ``octree=True`` gives the classical octree
+  (b = 2 at every split) the paper compares against.
 * ``eq1_branching``, ``eq2_subcell``, ``eq3_cell_id``, ``eq5_range``: the
   equations of Section 3, one function each.
 
@@ -70,7 +75,12 @@ def _load():
         lib.oracle_eq5_range.argtypes = [D, D, D, D, I64, P, P]
         lib.oracle_build_tree.restype = None
         lib.oracle_build_tree.argtypes = [P, P, P, I64, I64, D, D, ctypes.c_int32,
+                                          ctypes.c_int32,
                                           P, P, I64, P, P, I64, P, P, P, I64, P]
+        lib.oracle_cell_lists.restype = I64
+        lib.oracle_cell_lists.argtypes = [P, P, P, P, I64, P, P, P, I64]
+        lib.oracle_cell_check.restype = I64
+        lib.oracle_cell_check.argtypes = [P, P, P, P, I64, P, P, P, P, I64]
         _lib = lib
     return _lib
 
@@ -132,6 +142,49 @@ def lists(x, y, z, h, rows=None):
     return c, offsets, nbrs[:total]
 
 
+def cell_lists(x, y, z, h):
+    """All rows by the cell list: (counts int64, offsets int64, nbrs int32)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.shape[0]
+    lib = _load()
+    c = np.empty(max(n, 1), dtype=np.int64)
+    o = np.empty(n + 1, dtype=np.int64)
+    got = lib.oracle_cell_lists(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, _ptr(c), _ptr(o),
+                                None, 0)
+    if got < 0:
+        raise MemoryError("oracle cell list: out of memory")
+    total = int(o[n])
+    nbrs = np.empty(max(total, 1), dtype=np.int32)
+    got = lib.oracle_cell_lists(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, _ptr(c), _ptr(o),
+                                _ptr(nbrs), total)
+    if got != total:
+        raise MemoryError("oracle cell list: out of memory")
+    return c[:n], o, nbrs[:total]
+
+
+def cell_check(x, y, z, h, counts, offsets, nbrs, max_bad: int = 64):
+    """Compares lists produced elsewhere (counts int32[n], offsets int64[n+1],
+    nbrs int32) with the cell list, row by row.  Returns (number of wrong
+    rows, sorted array of up to max_bad of them)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.shape[0]
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    nbrs = np.ascontiguousarray(nbrs, dtype=np.int32)
+    if counts.shape[0] != n or offsets.shape[0] != n + 1:
+        raise ValueError("counts must have n and offsets n + 1 entries")
+    if n and (offsets[-1] > nbrs.shape[0] or offsets.min() < 0
+              or (np.diff(offsets) < 0).any()):
+        return n, np.arange(min(n, max_bad), dtype=np.int64)
+    nb = nbrs if nbrs.shape[0] else np.zeros(1, dtype=np.int32)
+    bad = np.empty(max(max_bad, 1), dtype=np.int64)
+    k = _load().oracle_cell_check(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, _ptr(counts),
+                                  _ptr(offsets), _ptr(nb), _ptr(bad), max_bad)
+    if k < 0:
+        raise MemoryError("oracle cell check: out of memory")
+    return int(k), np.sort(bad[:min(k, max_bad)])
+
+
 def eq1_branching(n: int, s: int) -> int:
     return int(_load().oracle_eq1_branching(int(n), int(s)))
 
@@ -165,9 +218,10 @@ class Tree:
 
 
 def build_tree(x, y, z, s: int = 64, alpha: float = 0.5, beta: float = 0.5,
-               max_depth: int = 32) -> Tree:
+               max_depth: int = 32, octree: bool = False) -> Tree:
     """Algorithm 1 on all particles; leaves in canonical depth-first order
-    (sub-cells in Morton order of their coordinates), members ascending."""
+    (sub-cells in Morton order of their coordinates), members ascending.
+    octree=True: b = 2 at every split (the classical octree)."""
     x, y, z = map(_f64, (x, y, z))
     n = x.shape[0]
     leaf_cap = max(n, 1)
@@ -182,7 +236,8 @@ def build_tree(x, y, z, s: int = 64, alpha: float = 0.5, beta: float = 0.5,
     node_depth = np.zeros(node_cap, dtype=np.int32)
     stats = np.zeros(8, dtype=np.int64)
     _load().oracle_build_tree(_ptr(x), _ptr(y), _ptr(z), n, int(s), float(alpha),
-                              float(beta), int(max_depth), _ptr(leaf_cnt),
+                              float(beta), int(max_depth), 1 if octree else 0,
+                              _ptr(leaf_cnt),
                               _ptr(leaf_depth), leaf_cap, _ptr(members),
                               _ptr(b_hist), bh_len, _ptr(node_b), _ptr(node_n),
                               _ptr(node_depth), node_cap, _ptr(stats))
