@@ -49,10 +49,12 @@ def parse():
     ap.add_argument("--bucket", type=int, default=0, help="single set: bucket size (0 = tuned)")
     ap.add_argument("--tune-cache", default=None, help="autotuner JSON cache (default: package)")
     ap.add_argument("--tune-out", default=None, help="write the cache here after tuning")
+    ap.add_argument("--tune-budget", type=float, default=120.0,
+                    help="seconds of tuning allowed for absent or stale cache keys (0: none)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-compare", action="store_true", help="skip the comparison forms")
     ap.add_argument("--no-single", action="store_true",
-                    help="Batch64: skip the single-set P8M and P16M blocks")
+                    help="Batch64: skip the single-set blocks (P8M, P16M, L1M, U10k)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     return ap.parse_args()
 
@@ -300,39 +302,29 @@ def bench_batch(a, tuner):
 
 
 def cpu_baseline_sets(sets, budget_s):
-    """The oracle (brute-force FP64 rows) on a bounded sample: rows drawn at
-    random over the sets (weighted by size), each tested against every
-    particle of its set; particles/s = rows / wall time."""
+    """The oracle's cell list (every row of a set, FP64, OpenMP over rows) on
+    a bounded sample: whole sets of the workload in a seeded random order
+    until the budget is spent; particles/s = particles of the sets done /
+    their wall time."""
     import numpy as np
     import oracle
     oracle.build(force=False)
     rng = np.random.default_rng(12345)
-    sizes = np.array([len(s[0]) for s in sets], dtype=np.float64)
-    w = sizes / sizes.sum()
-
-    def run(m):
-        pick = rng.choice(len(sets), m, p=w)
+    order = rng.permutation(len(sets))
+    done, npart, dt = [], 0, 0.0
+    for k in order:
+        x, y, z, h = sets[k]
         t0 = time.perf_counter()
-        for k in np.unique(pick):
-            x, y, z, h = sets[k]
-            rows = rng.integers(0, len(x), int((pick == k).sum()))
-            oracle.counts(x, y, z, h, rows)
-        return time.perf_counter() - t0
-
-    # Grow the sample until a run is long enough to extrapolate from (small
-    # runs are dominated by per-call overheads), then size it to the budget.
-    m = 64
-    dt = run(m)
-    while dt < 0.25 * budget_s:
-        m = int(m * min(8.0, max(2.0, 0.5 * budget_s / max(dt, 1e-6))))
-        dt = run(m)
-    if dt < 0.75 * budget_s:
-        m = int(m * budget_s / dt)
-        dt = run(m)
+        oracle.cell_lists(x, y, z, h)
+        dt += time.perf_counter() - t0
+        done.append(int(k))
+        npart += len(x)
+        if dt >= budget_s:
+            break
     cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
-    return {"value": m / dt, "unit": "particles/s", "cores": cores, "kind": "oracle",
-            "sample": "%d rows drawn over the %d sets (weighted by size), each tested against "
-                      "every particle of its set (%.1f s)" % (m, len(sets), dt)}
+    return {"value": npart / dt, "unit": "particles/s", "cores": cores, "kind": "oracle",
+            "sample": "oracle cell list (all rows, FP64) over %d of the %d sets, %d particles "
+                      "(%.1f s)" % (len(done), len(sets), npart, dt)}
 
 
 def main():
@@ -342,7 +334,8 @@ def main():
               "(--gpus %d requested)" % a.gpus, file=sys.stderr)
         sys.exit(2)
     from paper_1910_02639_amd import autotune
-    tuner = autotune.Tuner(a.tune_cache or autotune.CACHE)
+    tuner = autotune.Tuner(a.tune_cache or autotune.CACHE, tune_missing=a.tune_budget > 0,
+                           budget_s=a.tune_budget)
     if a.workload == "Batch64":
         out, sets = bench_batch(a, tuner)
         if not a.no_single:
@@ -354,6 +347,15 @@ def main():
                 k: p16[k] for k in ("n", "params", "value", "ms_per_step", "phases_ms",
                                     "neighbours_total", "pair_tests_per_particle",
                                     "fp64_confirmed_fraction", "exhaustive_items", "search_hbm")}
+            for name in ("L1M", "U10k"):
+                r, _ = bench_single(name, "fp32", max(2, min(a.steps, 10)), 2, not a.no_compare,
+                                    tuner)
+                out["single_set_" + name] = {
+                    k: r[k] for k in ("n", "params", "value", "ms_per_step", "phases_ms",
+                                      "neighbours_total", "pair_tests_per_particle",
+                                      "fp64_confirmed_fraction", "tree", "roofline",
+                                      "search_hbm", "fp64_plain", "fp32_filter_speedup")
+                    if k in r}
     else:
         r, xyzh = bench_single(a.workload, a.precision, a.steps, a.warmup, not a.no_compare,
                                tuner, a.bucket)
@@ -370,10 +372,11 @@ def main():
             if k in r:
                 out[k] = r[k]
         sets = [xyzh]
-    if tuner.tuned_now:
-        out["tuned_now"] = tuner.tuned_now
-        if a.tune_out:
-            tuner.save(a.tune_out)
+    out["tuning"] = {"tuned_now": tuner.tuned_now, "tune_s": round(tuner.spent_s, 1),
+                     "stale_entries_used": tuner.stale_used,
+                     "defaults_used": tuner.defaults_used}
+    if tuner.tuned_now and a.tune_out:
+        tuner.save(a.tune_out)
     if not a.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline_sets(sets, a.cpu_seconds)

@@ -4,12 +4,19 @@ Outputs never depend on s or beta, so a tuned choice can only change speed.
 A particle set is keyed by (precision, distribution class, floor(log2 n));
 the class separates sets with one smoothing length everywhere ("const_h",
 e.g. a uniform cube) from sets whose h varies ("graded_h", e.g. a Plummer
-sphere, whose density spans orders of magnitude).  A missing key is tuned on
-the GPU by btree_tune (every candidate built and searched, median of
-repeats) on the first set that needs it, and stored.
+sphere, whose density spans orders of magnitude).  Every cache entry records
+a hash of the kernel sources it was timed on.  A missing key, or one timed
+on other sources, is tuned on the GPU by btree_tune (every candidate built
+and searched, median of repeats) on the first set that needs it, with one
+progress line per key on stderr, within an optional time budget; past the
+budget (or with tuning switched off) a stale entry is still used (it is a
+valid choice, only perhaps no longer the fastest) and a missing one falls
+back to the library defaults.
 """
 from __future__ import annotations
 
+import sys
+import time
 import ctypes
 import json
 import math
@@ -17,7 +24,7 @@ import os
 
 import numpy as np
 
-from . import btree
+from . import btree, profiling
 
 CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
@@ -92,28 +99,72 @@ def tune(x, y, z, h, precision="fp32", sp: TuneSpace | None = None, stream=None)
             "alpha": float(best.alpha), "ms": float(best_ms.value), "n": n, "table": grid}
 
 
-class Tuner:
-    """JSON-backed cache of tuned parameters."""
+def kernels_hash() -> str:
+    """Hash of every kernel source of the library (code lines only)."""
+    return profiling.source_hash(profiling.ALL_SOURCES)
 
-    def __init__(self, path: str = CACHE, sp: TuneSpace | None = None):
+
+class Tuner:
+    """JSON-backed cache of tuned parameters.
+
+    tune_missing: tune keys that are absent or stale (else use what is there,
+    or the defaults).  budget_s: total seconds of tuning this object may
+    spend; keys met after that are treated as with tune_missing=False."""
+
+    def __init__(self, path: str = CACHE, sp: TuneSpace | None = None,
+                 tune_missing: bool = True, budget_s: float | None = None, log=None):
         self.path = path
         self.sp = sp
+        self.tune_missing = tune_missing
+        self.budget_s = budget_s
+        self.spent_s = 0.0
         self.entries = {}
         if path and os.path.exists(path):
             with open(path) as f:
                 self.entries = json.load(f)
-        self.tuned_now = []
+        self.hash = kernels_hash()
+        self.tuned_now = []   # keys tuned by this object
+        self.stale_used = []  # keys used although timed on other sources
+        self.defaults_used = []  # keys with no entry that were not tuned
+        self._log = log if log is not None else (
+            lambda *a: print("[tune %s]" % time.strftime("%H:%M:%S"), *a, file=sys.stderr,
+                             flush=True))
 
     def save(self, path: str | None = None):
         p = path or self.path
         with open(p, "w") as f:
             json.dump(self.entries, f, indent=1, sort_keys=True)
 
+    def fresh(self, k: str) -> bool:
+        e = self.entries.get(k)
+        return bool(e) and e.get("source_hash") == self.hash
+
     def params_for(self, x, y, z, h, precision="fp32") -> dict:
-        """Parameters for one set (device tensors), tuning its key if new."""
-        k = key(int(x.shape[0]), h, precision)
-        if k not in self.entries:
-            self.entries[k] = tune(x, y, z, h, precision, self.sp)
-            self.tuned_now.append(k)
+        """Parameters for one set (device tensors), tuning its key if new or
+        stale (and allowed)."""
+        n = int(x.shape[0])
+        k = key(n, h, precision)
+        if not self.fresh(k):
+            can = self.tune_missing and (self.budget_s is None or self.spent_s < self.budget_s)
+            if can:
+                self._log("tuning %s (n = %d, %d candidates)" % (
+                    k, n, (self.sp.n_bucket * self.sp.n_beta) if self.sp else 27))
+                t0 = time.perf_counter()
+                e = tune(x, y, z, h, precision, self.sp)
+                dt = time.perf_counter() - t0
+                self.spent_s += dt
+                e["source_hash"] = self.hash
+                e["tune_s"] = dt
+                self.entries[k] = e
+                self.tuned_now.append(k)
+                self._log("tuned %s: s = %d, beta = %g, %.3f ms (%.1f s)" % (
+                    k, e["bucket_size"], e["beta"], e["ms"], dt))
+            elif k in self.entries:
+                if k not in self.stale_used:
+                    self.stale_used.append(k)
+            else:
+                if k not in self.defaults_used:
+                    self.defaults_used.append(k)
+                return {}
         e = self.entries[k]
         return {"bucket_size": e["bucket_size"], "beta": e["beta"], "alpha": e["alpha"]}

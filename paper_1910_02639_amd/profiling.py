@@ -26,13 +26,19 @@ import sys
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def source_hash():
-    """Hash of the search kernel sources the traffic figures belong to, over
-    their code only (line comments and blank lines do not count)."""
+SEARCH_SOURCES = ("find.hip", "common.h", "prim.h")
+ALL_SOURCES = ("scan.hip", "sort.hip", "build.hip", "find.hip", "api.hip", "batch.hip",
+               "common.h", "prim.h")
+
+
+def source_hash(files=SEARCH_SOURCES):
+    """Hash of kernel sources (by default the search's, which the traffic
+    figures belong to), over their code only (line comments and blank lines
+    do not count)."""
     import hashlib
     import re
     h = hashlib.sha256()
-    for f in ("find.hip", "common.h", "prim.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_1910_02639_amd", "csrc", f)) as fh:
             for line in fh:
                 code = re.sub(r"//.*", "", line).strip()

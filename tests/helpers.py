@@ -56,3 +56,15 @@ def check_csr_invariants(counts, offsets, nbrs, n):
         bad = np.nonzero(np.diff(nbrs.astype(np.int64)) <= 0)[0] + 1
         starts = set(offsets[:-1].tolist())
         assert all(int(b) in starts for b in bad)
+
+
+def assert_all_rows(x, y, z, h, counts, offsets, nbrs, what=""):
+    """Every row of GPU lists against the oracle's cell list (the same
+    definition as the brute force, pinned to it byte for byte), plus the
+    CSR shape: offsets[0] = 0, offsets[n] = number of entries."""
+    import oracle
+    counts = np.ascontiguousarray(counts, dtype=np.int32)
+    assert offsets[0] == 0, what
+    assert offsets[-1] == nbrs.shape[0], what
+    k, bad = oracle.cell_check(x, y, z, h, counts, offsets, nbrs)
+    assert k == 0, "%s: %d rows differ from the oracle, first %s" % (what, k, bad[:10].tolist())

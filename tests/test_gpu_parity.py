@@ -8,7 +8,8 @@ import pytest
 
 import oracle
 from paper_1910_02639_amd import workloads as W
-from tests.helpers import (assert_same_lists, check_csr_invariants, gpu_lists, log, to_dev)
+from tests.helpers import (assert_all_rows, assert_same_lists, check_csr_invariants, gpu_lists,
+                           log, to_dev)
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +57,7 @@ def test_plummer_small_full(prec):
     got = gpu_lists(x, y, z, h, prec, bucket_size=32)
     want = oracle.lists(x, y, z, h)
     assert_same_lists(got, want)
+    log("plummer 30k exhaustive", got[3]["brute_chunks"], "split", got[3]["split_items"])
     # At n = 3e4 the outermost particles have 2h ~ 7 (h grows as rho^-1/3),
     # so their work items see most of the sphere: they are split, and the
     # queries whose own box is too full take the exhaustive path.
@@ -160,11 +162,7 @@ def test_lattice_1m(prec):
     assert o[-1] == 90_205_144
     assert np.array_equal(c, _lattice_expected_counts())
     assert st["depth"] == 1 and st["n_leaves"] == 8000 and st["b_hist"] == {20: 1}
-    rng = np.random.default_rng(7)
-    rows = np.unique(np.concatenate([[0, 1, 99, 10_000, 999_999, 505_050],
-                                     rng.integers(0, len(x), 200)]))
-    want = oracle.lists(x, y, z, h, rows)
-    assert_same_lists((c, o, nb), want, rows)
+    assert_all_rows(x, y, z, h, c, o, nb, "L1M %s" % prec)
     # constant h: lists are symmetric
     r = np.repeat(np.arange(len(x), dtype=np.int64), c)
     fwd = r * len(x) + nb
@@ -173,39 +171,26 @@ def test_lattice_1m(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
-def test_plummer_8m_sampled(prec):
+def test_plummer_8m_all_rows(prec):
+    """P8M (8M-particle Plummer sphere), both arithmetic forms: every row
+    equals the oracle's."""
     x, y, z, h = W.plummer(8_000_000, 0)
     log("P8M", prec)
     c, o, nb, st = gpu_lists(x, y, z, h, prec, bucket_size=128)
-    log("P8M total", int(o[-1]), st)
-    check_csr_invariants(c, o, nb, len(x))
-    r = np.sqrt(x * x + y * y + z * z)
-    rng = np.random.default_rng(3)
-    core = np.argsort(r)[:20]
-    edge = np.argsort(r)[-20:]
-    rows = np.unique(np.concatenate([core, edge, rng.integers(0, len(x), 260)]))
-    want = oracle.lists(x, y, z, h, rows)
-    assert_same_lists((c, o, nb), want, rows)
+    log("P8M total", int(o[-1]), "exhaustive", st["brute_chunks"], "split", st["split_items"])
+    assert_all_rows(x, y, z, h, c, o, nb, "P8M %s" % prec)
     assert st["brute_chunks"] == 0
 
 
 def test_plummer_16m_precision_form():
     """The precision-form configuration: a 16M-particle Plummer sphere with
-    the FP32 filter and FP64 band confirmation.  Sampled rows (core, edge,
-    random) equal the oracle's; every entry count and offset is consistent;
-    the confirmed fraction is small but the band is exercised."""
+    the FP32 filter and FP64 band confirmation.  Every row equals the
+    oracle's; the confirmed fraction is small but the band is exercised."""
     x, y, z, h = W.plummer(16_000_000, 0)
     log("P16M")
     c, o, nb, st = gpu_lists(x, y, z, h, "fp32", bucket_size=256, beta=0.8)
     log("P16M total", int(o[-1]), st["fp64_confirms"], st["pair_tests"])
-    check_csr_invariants(c, o, nb, len(x))
-    r = np.sqrt(x * x + y * y + z * z)
-    rng = np.random.default_rng(4)
-    core = np.argsort(r)[:16]
-    edge = np.argsort(r)[-16:]
-    rows = np.unique(np.concatenate([core, edge, rng.integers(0, len(x), 200)]))
-    want = oracle.lists(x, y, z, h, rows)
-    assert_same_lists((c, o, nb), want, rows)
+    assert_all_rows(x, y, z, h, c, o, nb, "P16M")
     assert 0 < st["fp64_confirms"] < st["pair_tests"] * 1e-5
 
 
