@@ -275,6 +275,43 @@ btree_status btree_tune(const double* x, const double* y, const double* z,
                         const btree_tune_space* space, btree_params* best,
                         double* best_ms, double* all_ms, void* hip_stream);
 
+/* ------------------------------------------------------------------------
+ * Build and search with no device allocation.
+ * ---------------------------------------------------------------------- */
+#define BTREE_NOALLOC_MAX_N 65536       /* particles per call, at most       */
+#define BTREE_NOALLOC_SCRATCH_MIB 128   /* fixed device scratch per GPU      */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * result as btree_build + btree_find_neighbors (both passes) + btree_destroy
+ * on one set of n particles, with every tree, work-list and row buffer
+ * carved from a fixed device array of BTREE_NOALLOC_SCRATCH_MIB MiB that the
+ * library holds on each GPU it runs on from load until the process ends.
+ * The call makes no hipMalloc or hipFree and allocates through no other
+ * library; the caller passes inputs and outputs.
+ *
+ * x, y, z, h: device FP64[n], 0 <= n <= BTREE_NOALLOC_MAX_N.
+ * p: parameters (NULL = defaults); timing must be 0.
+ * counts: device int32[n]; offsets: device int64[n+1]; nbrs: device
+ *   int32[capacity] (NULL allowed when capacity = 0); rows as in
+ *   btree_find_neighbors.  total: host int64, receives offsets[n].
+ * Synchronises hip_stream before returning.  Calls on one GPU share its
+ * scratch: the library serialises calls from different host threads on
+ * one device, and a call must not overlap other work that uses the
+ * scratch (there is none besides this entry point).
+ * Errors: EINVAL (n above BTREE_NOALLOC_MAX_N, NULL arrays, bad parameters
+ *   or particle data: nothing written), EOVERFLOW (capacity < total: counts,
+ *   offsets and *total written, nbrs not), ENOMEM (this input's tree, work
+ *   lists and rows need more than the scratch holds; the message says how
+ *   much; about 1 KB per particle plus 4 B per neighbour entry fit at the
+ *   default bucket size, several times more at bucket sizes near 1), EDEVICE. */
+btree_status btree_find_neighbors_noalloc(const double* x, const double* y,
+                                          const double* z, const double* h,
+                                          int64_t n, const btree_params* p,
+                                          int32_t* counts, int64_t* offsets,
+                                          int32_t* nbrs, int64_t capacity,
+                                          int64_t* total, void* hip_stream);
+
 /* Message of the last failed call on this host thread ("" if none). */
 const char* btree_last_error(void);
 

@@ -30,7 +30,10 @@ STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFL
 SYMBOLS = ["btree_params_default", "btree_build", "btree_rebuild", "btree_find_neighbors",
            "btree_stats", "btree_export", "btree_destroy", "btree_last_error",
            "btree_batch_create", "btree_batch_run", "btree_batch_stats", "btree_batch_destroy",
-           "btree_batch_graph_counts", "btree_tune_space_default", "btree_tune"]
+           "btree_batch_graph_counts", "btree_tune_space_default", "btree_tune",
+           "btree_find_neighbors_noalloc"]
+
+NOALLOC_MAX_N = 65536
 
 
 class Params(ctypes.Structure):
@@ -99,6 +102,9 @@ def lib():
         L.btree_batch_destroy.argtypes = [P]
         L.btree_batch_graph_counts.restype = ctypes.c_int
         L.btree_batch_graph_counts.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+        L.btree_find_neighbors_noalloc.restype = ctypes.c_int
+        L.btree_find_neighbors_noalloc.argtypes = [P, P, P, P, I64, ctypes.POINTER(Params), P,
+                                                   P, P, I64, ctypes.POINTER(I64), P]
         _lib = L
     return _lib
 
@@ -369,3 +375,31 @@ def find_neighbors(x, y, z, h, bucket_size=64, alpha=0.5, beta=0.5, max_depth=32
     """BuildTree + FindNeighbors in one call; returns (counts, offsets, nbrs)."""
     with BTree(x, y, z, bucket_size, alpha, beta, max_depth, precision, stream) as t:
         return t.find(h, stream=stream)
+
+
+def find_neighbors_noalloc(x, y, z, h, counts, offsets, nbrs, bucket_size=64, alpha=0.5,
+                           beta=0.5, max_depth=32, precision="fp32", stream=None):
+    """btree_find_neighbors_noalloc into caller buffers (counts int32[n],
+    offsets int64[n+1], nbrs int32 of any capacity, or None): BuildTree and
+    FindNeighbors with no device allocation.  Returns the total; raises
+    BTreeError (EOVERFLOW when nbrs is too small: counts and offsets are then
+    valid and the error's `total` holds the total)."""
+    n = int(x.shape[0])
+    for a, nm in ((x, "x"), (y, "y"), (z, "z"), (h, "h")):
+        _dev_f64(a, nm)
+        if a.shape[0] != n:
+            raise ValueError("x, y, z, h must have the same length")
+    p = params(bucket_size, alpha, beta, max_depth, precision)
+    total = ctypes.c_int64()
+    cap = int(nbrs.numel()) if nbrs is not None else 0
+    st = lib().btree_find_neighbors_noalloc(
+        ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+        ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(h.data_ptr()), n, ctypes.byref(p),
+        ctypes.c_void_p(counts.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+        ctypes.c_void_p(nbrs.data_ptr()) if nbrs is not None else None, cap,
+        ctypes.byref(total), _stream(stream))
+    if st != BTREE_OK:
+        e = BTreeError(st, last_error())
+        e.total = int(total.value)
+        raise e
+    return int(total.value)

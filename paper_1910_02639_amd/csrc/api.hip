@@ -2,6 +2,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "common.h"
@@ -12,6 +13,43 @@ static thread_local std::string g_err;
 
 void set_error(const std::string& msg) { g_err = msg; }
 const char* get_error() { return g_err.c_str(); }
+
+Arena*& current_arena() {
+    static thread_local Arena* a = nullptr;
+    return a;
+}
+
+// Makes an arena current on this host thread for the lifetime of the scope.
+struct ArenaScope {
+    Arena* prev;
+    explicit ArenaScope(Arena* a) : prev(current_arena()) { current_arena() = a; }
+    ~ArenaScope() { current_arena() = prev; }
+};
+
+// The scratch of the entry point that allocates no device memory: one
+// fixed array per GPU, present from module load until the process ends.
+// Host code must not use this name as a device address: each device's
+// address comes from hipGetSymbolAddress (noalloc_scratch below).
+constexpr size_t kNoAllocBytes = (size_t)BTREE_NOALLOC_SCRATCH_MIB << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+constexpr int kMaxDevices = 64;
+static void* g_noalloc_ptr[kMaxDevices];
+static std::mutex g_noalloc_mu[kMaxDevices];
+
+// Device address of `scratch` on the current device `dev`, looked up once
+// per device with that device current (the caller holds its mutex).
+static char* noalloc_scratch(int dev) {
+    if (!g_noalloc_ptr[dev]) {
+        void* ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            fail(BTREE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") +
+                                    hipGetErrorString(e));
+        g_noalloc_ptr[dev] = ptr;
+    }
+    return static_cast<char*>(g_noalloc_ptr[dev]);
+}
 
 static void check_params(const btree_params& p) {
     if (p.bucket_size < 1) fail(BTREE_EINVAL, "bucket_size must be >= 1");
@@ -266,6 +304,65 @@ btree_status btree_destroy(btree_handle H) {
     (void)hipDeviceSynchronize();
     delete H;
     return BTREE_OK;
+}
+
+btree_status btree_find_neighbors_noalloc(const double* x, const double* y, const double* z,
+                                          const double* h, int64_t n, const btree_params* p,
+                                          int32_t* counts, int64_t* offsets, int32_t* nbrs,
+                                          int64_t capacity, int64_t* total, void* hip_stream) {
+    return guarded([&] {
+        if (!total) fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: total is NULL");
+        if (n < 0 || n > BTREE_NOALLOC_MAX_N)
+            fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: n = " + std::to_string(n) +
+                                   " is outside [0, " + std::to_string(BTREE_NOALLOC_MAX_N) + "]");
+        if (!offsets) fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: offsets is NULL");
+        if (n > 0 && (!h || !counts))
+            fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: NULL h or counts");
+        if (capacity < 0 || (capacity > 0 && !nbrs))
+            fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: bad capacity or NULL nbrs");
+        btree_params prm;
+        if (p) prm = *p;
+        else btree_params_default(&prm);
+        check_params(prm);
+        if (prm.timing) fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: timing must be 0");
+        check_n(n, x, y, z, prm.bucket_size);
+        int dev = 0;
+        BT_HIP(hipGetDevice(&dev));
+        if (dev < 0 || dev >= kMaxDevices)
+            fail(BTREE_EDEVICE, "btree_find_neighbors_noalloc: device id above 63");
+        std::lock_guard<std::mutex> lock(g_noalloc_mu[dev]);
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        Arena arena;
+        arena.base = noalloc_scratch(dev);
+        arena.size = kNoAllocBytes;
+        ArenaScope scope(&arena);
+        // Every buffer of this tree is carved from the scratch; the tree's
+        // host side lives on this call's stack.
+        Tree t;
+        t.prm = prm;
+        t.device = dev;
+        try {
+            do_build(&t, x, y, z, n, st);
+            if (n == 0) {
+                BT_HIP(hipMemsetAsync(offsets, 0, sizeof(int64_t), st));
+                *total = 0;
+            } else {
+                const int64_t tot = find_pass1(t, h, counts, offsets, st);
+                *total = tot;
+                if (capacity < tot)
+                    fail(BTREE_EOVERFLOW, "btree_find_neighbors_noalloc: capacity " +
+                                              std::to_string(capacity) + " < total " +
+                                              std::to_string(tot));
+                find_fill(t, counts, offsets, nbrs, capacity, nullptr, false, st);
+            }
+            // The next call on this device reuses the scratch.
+            BT_HIP(hipStreamSynchronize(st));
+        } catch (...) {
+            (void)hipStreamSynchronize(st);
+            throw;
+        }
+        set_error("");
+    });
 }
 
 btree_status btree_tune_space_default(btree_tune_space* sp) {

@@ -46,23 +46,56 @@ struct Fail {
     throw Fail{code};
 }
 
-// Device buffer owned by a handle; grows on demand, never shrinks.
+// A device region that buffers are carved from instead of hipMalloc: a bump
+// allocator over [base, base + size), for the entry point that allocates no
+// device memory.  Nothing carved is ever freed; the region is reused from
+// its start by the next call.
+struct Arena {
+    char* base = nullptr;  // device address of the region
+    size_t size = 0;       // bytes
+    size_t used = 0;       // bytes handed out so far
+};
+
+// The arena this host thread's buffers come from, or null (hipMalloc).
+Arena*& current_arena();
+
+inline void* arena_take(Arena* a, size_t b) {
+    const size_t at = (a->used + 255) & ~(size_t)255;
+    if (at > a->size || b > a->size - at)
+        fail(BTREE_ENOMEM, "the no-allocation scratch (" + std::to_string(a->size) +
+                               " bytes) is exhausted: " + std::to_string(b) +
+                               " more bytes needed after " + std::to_string(a->used));
+    a->used = at + b;
+    return a->base + at;
+}
+
+// Device buffer owned by a handle; grows on demand, never shrinks.  While
+// an arena is current on the host thread, memory is carved from it (and
+// `borrowed`: never freed).
 struct DBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool borrowed = false;
     DBuf() = default;
     DBuf(const DBuf&) = delete;
     DBuf& operator=(const DBuf&) = delete;
     ~DBuf() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p && !borrowed) (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     void reserve(size_t want) {
         if (want <= bytes) return;
         release();
         size_t b = want < 256 ? 256 : want;
+        if (Arena* a = current_arena()) {
+            p = arena_take(a, b);
+            bytes = b;
+            borrowed = true;
+            return;
+        }
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             p = nullptr;
@@ -76,21 +109,27 @@ struct DBuf {
         if (want <= bytes) return;
         size_t b = want + want / 2;
         void* q = nullptr;
-        hipError_t e = hipMalloc(&q, b);
-        if (e != hipSuccess)
-            fail(e == hipErrorOutOfMemory ? BTREE_ENOMEM : BTREE_EDEVICE,
-                 "hipMalloc of " + std::to_string(b) + " bytes: " + hipGetErrorString(e));
+        Arena* a = current_arena();
+        if (a) {
+            q = arena_take(a, b);
+        } else {
+            hipError_t e = hipMalloc(&q, b);
+            if (e != hipSuccess)
+                fail(e == hipErrorOutOfMemory ? BTREE_ENOMEM : BTREE_EDEVICE,
+                     "hipMalloc of " + std::to_string(b) + " bytes: " + hipGetErrorString(e));
+        }
         if (p && keep) {
-            e = hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, st);
+            hipError_t e = hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) {
-                (void)hipFree(q);
+                if (!a) (void)hipFree(q);
                 fail(BTREE_EDEVICE, std::string("grow copy: ") + hipGetErrorString(e));
             }
         }
         release();
         p = q;
         bytes = b;
+        borrowed = a != nullptr;
     }
     template <class T> T* as() const { return static_cast<T*>(p); }
 };

@@ -1702,6 +1702,10 @@ void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t*
 // k_place alone (not inside a graph capture).
 void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
                int64_t capacity, int64_t* totals, bool time_place, hipStream_t st) {
+    // The kernels below read counts and offsets of every particle (nbrs may
+    // be null with a capacity of 0: nothing is written then).
+    if (t.n > 0 && (!counts || !offsets))
+        fail(BTREE_EDEVICE, "find_fill: counts or offsets missing");
     hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
                        t.sets.as<SetDev>(), t.pos.as<double4>(), t.orig.as<double4>(),
