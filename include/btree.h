@@ -67,7 +67,15 @@ typedef struct {
     int32_t timing;         /* 1: time each phase with HIP events recorded on
                                the caller's stream (btree_stats.phase_ms);
                                default 0                                      */
-    int32_t reserved[5];    /* must be zero                                   */
+    int32_t exclude_self;   /* 1: row i does not list i itself (the method's
+                               search, Algorithm 2, tests p against itself
+                               and lists it when h_p > 0); default 0; in a
+                               batch every set must agree                     */
+    int32_t octree;         /* 1: every split uses b = 2 (the classical octree
+                               of Section 2 that the paper compares against;
+                               b = 2 is the floor of Section 3.1 step 3),
+                               with no Eq. 1 / Eq. 4; default 0               */
+    int32_t reserved[3];    /* must be zero                                   */
 } btree_params;
 
 /* Shape of a built tree and counters of the last search. */

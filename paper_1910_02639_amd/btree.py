@@ -40,7 +40,8 @@ class Params(ctypes.Structure):
     _fields_ = [("bucket_size", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("beta", ctypes.c_double), ("max_depth", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("group_size", ctypes.c_int32),
-                ("timing", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("timing", ctypes.c_int32), ("exclude_self", ctypes.c_int32),
+                ("octree", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class Stats(ctypes.Structure):
@@ -119,7 +120,7 @@ def _check(status):
 
 
 def params(bucket_size=64, alpha=0.5, beta=0.5, max_depth=32, precision="fp32",
-           group_size=0, timing=False) -> Params:
+           group_size=0, timing=False, exclude_self=False, octree=False) -> Params:
     p = Params()
     _check(lib().btree_params_default(ctypes.byref(p)))
     p.bucket_size = int(bucket_size)
@@ -134,6 +135,8 @@ def params(bucket_size=64, alpha=0.5, beta=0.5, max_depth=32, precision="fp32",
         raise ValueError("precision must be 'fp32' or 'fp64'")
     p.group_size = int(group_size)
     p.timing = 1 if timing else 0
+    p.exclude_self = 1 if exclude_self else 0
+    p.octree = 1 if octree else 0
     return p
 
 
@@ -158,7 +161,8 @@ class BTree:
     """A b-tree built on the GPU (btree_build) over FP64 coordinates."""
 
     def __init__(self, x, y, z, bucket_size=64, alpha=0.5, beta=0.5, max_depth=32,
-                 precision="fp32", stream=None, timing=False):
+                 precision="fp32", stream=None, timing=False, exclude_self=False,
+                 octree=False):
         x = _dev_f64(x, "x")
         y = _dev_f64(y, "y")
         z = _dev_f64(z, "z")
@@ -167,7 +171,8 @@ class BTree:
         self.n = int(x.shape[0])
         self.device = x.device
         self._keep = (x, y, z)
-        p = params(bucket_size, alpha, beta, max_depth, precision, timing=timing)
+        p = params(bucket_size, alpha, beta, max_depth, precision, timing=timing,
+                   exclude_self=exclude_self, octree=octree)
         h = ctypes.c_void_p()
         _check(lib().btree_build(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                  ctypes.c_void_p(z.data_ptr()), self.n, ctypes.byref(p),
@@ -378,7 +383,8 @@ def find_neighbors(x, y, z, h, bucket_size=64, alpha=0.5, beta=0.5, max_depth=32
 
 
 def find_neighbors_noalloc(x, y, z, h, counts, offsets, nbrs, bucket_size=64, alpha=0.5,
-                           beta=0.5, max_depth=32, precision="fp32", stream=None):
+                           beta=0.5, max_depth=32, precision="fp32", stream=None,
+                           exclude_self=False, octree=False):
     """btree_find_neighbors_noalloc into caller buffers (counts int32[n],
     offsets int64[n+1], nbrs int32 of any capacity, or None): BuildTree and
     FindNeighbors with no device allocation.  Returns the total; raises
@@ -389,7 +395,8 @@ def find_neighbors_noalloc(x, y, z, h, counts, offsets, nbrs, bucket_size=64, al
         _dev_f64(a, nm)
         if a.shape[0] != n:
             raise ValueError("x, y, z, h must have the same length")
-    p = params(bucket_size, alpha, beta, max_depth, precision)
+    p = params(bucket_size, alpha, beta, max_depth, precision, exclude_self=exclude_self,
+               octree=octree)
     total = ctypes.c_int64()
     cap = int(nbrs.numel()) if nbrs is not None else 0
     st = lib().btree_find_neighbors_noalloc(

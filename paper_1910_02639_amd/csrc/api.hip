@@ -60,7 +60,9 @@ static void check_params(const btree_params& p) {
         fail(BTREE_EINVAL, "precision must be BTREE_FP64 or BTREE_FP32_FILTER");
     if (p.group_size != 0 && p.group_size != kGroup) fail(BTREE_EINVAL, "group_size must be 0 or 64");
     if (p.timing != 0 && p.timing != 1) fail(BTREE_EINVAL, "timing must be 0 or 1");
-    for (int k = 0; k < 5; ++k)
+    if (p.exclude_self != 0 && p.exclude_self != 1) fail(BTREE_EINVAL, "exclude_self must be 0 or 1");
+    if (p.octree != 0 && p.octree != 1) fail(BTREE_EINVAL, "octree must be 0 or 1");
+    for (int k = 0; k < 3; ++k)
         if (p.reserved[k] != 0) fail(BTREE_EINVAL, "reserved fields must be zero");
 }
 

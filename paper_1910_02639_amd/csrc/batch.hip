@@ -60,7 +60,11 @@ void check_set_params(const btree_params& p, const btree_params& p0) {
     if (p.group_size != 0 && p.group_size != kGroup) fail(BTREE_EINVAL, "group_size must be 0 or 64");
     if (p.timing != 0 && p.timing != 1) fail(BTREE_EINVAL, "timing must be 0 or 1");
     if (p.timing != p0.timing) fail(BTREE_EINVAL, "all sets of a batch need one timing flag");
-    for (int k = 0; k < 5; ++k)
+    if (p.exclude_self != 0 && p.exclude_self != 1) fail(BTREE_EINVAL, "exclude_self must be 0 or 1");
+    if (p.exclude_self != p0.exclude_self)
+        fail(BTREE_EINVAL, "all sets of a batch need one exclude_self flag");
+    if (p.octree != 0 && p.octree != 1) fail(BTREE_EINVAL, "octree must be 0 or 1");
+    for (int k = 0; k < 3; ++k)
         if (p.reserved[k] != 0) fail(BTREE_EINVAL, "reserved fields must be zero");
 }
 

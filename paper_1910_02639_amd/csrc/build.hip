@@ -213,7 +213,7 @@ __global__ void k_candidates(Node* __restrict__ nodes, const SetDev* __restrict_
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m;
          i += (int64_t)gridDim.x * blockDim.x) {
         const Node& N = nodes[nb + i];
-        const int b = branching(N.n, sets[N.set].s);
+        const int b = first_branching(N.n, sets[N.set]);
         nodes[nb + i].b = b;
         int64_t sum = 0;
         for (int bb = b;; bb = halve(bb)) {
@@ -382,7 +382,7 @@ __global__ __launch_bounds__(kT) void k_select(Node* __restrict__ nodes,
         const double thr = S.alpha * (double)S.s;
         int64_t off = hoff[i];
         int rounds = 0;
-        int bb = branching(nodes[node].n, S.s);
+        int bb = first_branching(nodes[node].n, S);
         for (;; bb = halve(bb), ++rounds) {
             const int64_t nc = (int64_t)bb * bb * bb;
             int64_t under = 0;
@@ -1069,6 +1069,7 @@ void plan_sets(Tree& t, int32_t nsets, const int64_t* set_off_in, const btree_pa
         S.s = prm[k].bucket_size;
         S.max_depth = prm[k].max_depth;
         S.root = kEmpty;
+        S.octree = prm[k].octree;
         sd[k] = S;
         // Cells of one level are disjoint and hold more than s particles each.
         const int64_t q = S.n / (S.s + 1) + 1;

@@ -186,9 +186,16 @@ struct SetDev {
     int32_t s;         // bucket size
     int32_t max_depth;
     int32_t root;      // child code of the root cell (node id, leaf id | kLeafBit, or kEmpty)
-    int32_t pad;
+    int32_t octree;    // 1: b = 2 at every split (no Eq. 1 / Eq. 4)
     double box[6];     // root box: lo x, y, z, hi x, y, z
 };
+
+// First branching factor tried for a cell of n particles of set S: Eq. 1,
+// or 2 for the octree.
+__host__ __device__ inline int branching(int64_t n, int64_t s);
+__host__ __device__ inline int first_branching(int64_t n, const SetDev& S) {
+    return S.octree ? 2 : branching(n, S.s);
+}
 
 // Tiles of at most kTileN particles, never straddling two sets.
 struct Tile {

@@ -517,7 +517,8 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                                            int64_t* __restrict__ soff,
                                            int32_t* __restrict__ scratch, int64_t scap,
                                            unsigned long long* __restrict__ scur, int stripe,
-                                           Ctl* __restrict__ ctl, Stats* __restrict__ stats) {
+                                           Ctl* __restrict__ ctl, Stats* __restrict__ stats,
+                                           const int excl) {
     using E = typename Ent<F32>::T;
     constexpr int kMaxW = ((CMAX / kWaves) + 31) / 32;  // bit words per lane and wavefront
     __shared__ E s_cand[CMAX];
@@ -845,11 +846,12 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     struct Q {
         double x, y, z, R, r2;
         float ax, ay, az, lo, hi;
+        int idx;
     };
     auto query = [&](int q) -> Q {
         return Q{__shfl(qp.x, q, 64), __shfl(qp.y, q, 64), __shfl(qp.z, q, 64), __shfl(R, q, 64),
                  __shfl(r2q, q, 64),  __shfl(ax, q, 64),   __shfl(ay, q, 64),   __shfl(az, q, 64),
-                 __shfl(tlo, q, 64),  __shfl(thi, q, 64)};
+                 __shfl(tlo, q, 64),  __shfl(thi, q, 64),  __shfl(qidx, q, 64)};
     };
     // Hits of query Qd among chunk c.
     auto chunk_hits = [&](const Q& Qd, int c, unsigned long long& nconf) -> uint64_t {
@@ -870,13 +872,16 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 }
                 lo |= __ballot(ok);
             }
+            if (excl) lo &= ~__ballot(v && Ent<F32>::key(e) == Qd.idx);
             return lo;
         } else {
             const double dx = __dsub_rn(Qd.x, e.x), dy = __dsub_rn(Qd.y, e.y);
             const double dz = __dsub_rn(Qd.z, e.z);
             const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
                                         __dmul_rn(dz, dz));
-            return __ballot(v && d2 < Qd.r2);
+            uint64_t m = __ballot(v && d2 < Qd.r2);
+            if (excl) m &= ~__ballot(v && Ent<F32>::key(e) == Qd.idx);
+            return m;
         }
     };
 
@@ -995,6 +1000,28 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
 #pragma unroll
         for (int i = 0; i + 1 < kMaxW; ++i) wq[i] = wq[i + 1];
         wq[kMaxW - 1] = word;
+    }
+    // exclude_self: the query's own bit is cleared before anything is
+    // counted, so counts, row offsets and rows all leave it out.  The query
+    // lies inside its item's box, so it is one of the candidates; its place
+    // in the index-ordered list is found by bisection on the keys.
+    if (excl && !small && qv && r2q > 0.0 && C > 0) {
+        int lo = 0, hi = C - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (Ent<F32>::key(cand(mid)) < qidx) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo >= k0 && lo < k1 && Ent<F32>::key(cand(lo)) == qidx) {
+            const int slot = kMaxW - nw + ((lo - k0) >> 5);
+            const uint32_t bit = 0x80000000u >> ((lo - k0) & 31);
+#pragma unroll
+            for (int i = 0; i < kMaxW; ++i)
+                if (i == slot && (wq[i] & bit)) {
+                    wq[i] &= ~bit;
+                    --hits;
+                }
+        }
     }
     if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
     if (!small) s_cnt[w][lane] = hits;
@@ -1128,7 +1155,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                const int4* __restrict__ whdr,
                                                const int2* __restrict__ wl,
                                                const ItemBox* __restrict__ ibox,
-                                               Stats* __restrict__ stats) {
+                                               Stats* __restrict__ stats, const int excl) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     const int nch = ctl->n_chunks;
     const int ci = blockIdx.x;
@@ -1138,7 +1165,7 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     const Chunk ch = chunks[ci];
     const int C = sweep_item<F32, 1>(ci, ch, whdr, wl, ibox, pos, orig, nodes, ctab, leaves, lrange,
                                         sets, h, counts, soff, scratch, scap, scur,
-                                        stripe_of(ch.beg), ctl, stats);
+                                        stripe_of(ch.beg), ctl, stats, excl);
     if (C && threadIdx.x == 0) {
         const uint32_t k = atomicAdd(&ctl->nsplit, 1u);
         split[k] = Chunk{ch.beg, ch.cnt, ch.set, C};
@@ -1202,7 +1229,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
                                                      Ctl* __restrict__ ctl,
                                                      Chunk* __restrict__ brute,
                                                      int32_t* __restrict__ bcnt,
-                                                     Stats* __restrict__ stats) {
+                                                     Stats* __restrict__ stats, const int excl) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     // Units of this level: level 1 takes each listed item whole; levels 2
     // and 3 cut each listed unit into parts of kSubGroup queries or of one.
@@ -1233,7 +1260,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         const int ci = LEVEL == 1 ? split_ci[u] : -1;
         const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2)>(
             ci, unit, whdr, wl, LEVEL == 1 ? ibox : nullptr, pos, orig, nodes, ctab, leaves, lrange,
-            sets, h, counts, soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats);
+            sets, h, counts, soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats, excl);
         if (!C) continue;
         __syncthreads();
         if (LEVEL == 3 || (nset <= kDenseSet && C != kNoCount && 4 * (int64_t)C > nset)) {
@@ -1429,7 +1456,7 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
                                                int32_t* __restrict__ counts,
                                                const int64_t* __restrict__ offsets, int64_t n,
                                                int64_t capacity, int32_t* __restrict__ nbrs,
-                                               Ctl* __restrict__ ctl) {
+                                               Ctl* __restrict__ ctl, const int excl) {
     __shared__ double4 s_c[kDenseTile];
     __shared__ int32_t s_cnt[kWaves][64];
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
@@ -1498,6 +1525,10 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
                                           __dmul_rn(dz, dz));
                     }
                     push4_f64(word, d2[0], d2[1], d2[2], d2[3], r2);
+                }
+                if (excl) {  // the query's own bit (its index local to the set)
+                    const int64_t d = (int64_t)qidx - jb - (t0 + k0);
+                    if (d >= 0 && d < 32) word &= ~(0x80000000u >> d);
                 }
                 wd[b] = word;
                 mine += __popc(word);
@@ -1588,7 +1619,7 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipS
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.split_ci.as<int32_t>(),
                        t.whdr.as<int4>(), t.wl.as<int2>(), t.ibox.as<ItemBox>(),
-                       t.stats.as<Stats>());
+                       t.stats.as<Stats>(), t.prm.exclude_self);
     BT_LAUNCH();
 }
 
@@ -1602,7 +1633,7 @@ void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* 
                        t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.blist.as<Chunk>(), t.bset.as<int32_t>(),
-                       t.stats.as<Stats>());
+                       t.stats.as<Stats>(), t.prm.exclude_self);
     BT_LAUNCH();
 }
 
@@ -1681,7 +1712,7 @@ void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets
                        t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
                        t.sets.as<SetDev>(), t.pos.as<double4>(),
                        t.orig.as<double4>(), t.hs.as<double>(), counts, nullptr, t.n, (int64_t)0, nullptr,
-                       t.ctl.as<Ctl>());
+                       t.ctl.as<Ctl>(), t.prm.exclude_self);
     BT_LAUNCH();
     scan_exclusive_i32(counts, offsets, t.n, t, st, &t.ctl.as<Ctl>()->data_bad);
 }
@@ -1709,7 +1740,8 @@ void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* 
     hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
                        t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
                        t.sets.as<SetDev>(), t.pos.as<double4>(), t.orig.as<double4>(),
-                       t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs, t.ctl.as<Ctl>());
+                       t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs, t.ctl.as<Ctl>(),
+                       t.prm.exclude_self);
     BT_LAUNCH();
     if (time_place) t.timer.start(kPhPlace, st);
     find_place(t, counts, offsets, nbrs, capacity, st);

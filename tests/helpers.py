@@ -68,3 +68,15 @@ def assert_all_rows(x, y, z, h, counts, offsets, nbrs, what=""):
     assert offsets[-1] == nbrs.shape[0], what
     k, bad = oracle.cell_check(x, y, z, h, counts, offsets, nbrs)
     assert k == 0, "%s: %d rows differ from the oracle, first %s" % (what, k, bad[:10].tolist())
+
+
+def drop_self(counts, offsets, nbrs):
+    """CSR lists with every row's own index removed (j == i): the expected
+    result of exclude_self, from lists that include it."""
+    n = len(counts)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.asarray(counts, dtype=np.int64))
+    keep = nbrs.astype(np.int64) != rows
+    c = np.bincount(rows[keep], minlength=n).astype(np.int64)
+    o = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(c, out=o[1:])
+    return c, o, nbrs[keep]

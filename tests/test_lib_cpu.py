@@ -82,7 +82,8 @@ def _build(L, n, p=None, out=True, ptr=1):
 @pytest.mark.parametrize("field,value", [("bucket_size", 0), ("alpha", float("nan")),
                                          ("alpha", -1.0), ("beta", float("inf")),
                                          ("max_depth", -1), ("max_depth", 65),
-                                         ("precision", 7), ("group_size", 32)])
+                                         ("precision", 7), ("group_size", 32),
+                                         ("exclude_self", 2), ("octree", -1)])
 def test_build_rejects_bad_params(L, field, value):
     p = L.params()
     setattr(p, field, value)
@@ -165,6 +166,9 @@ def test_batch_create_rejects_bad_arguments(L):
     assert "bucket_size" in L.last_error()
     arr = (L.Params * 2)(L.params(), L.params(timing=True))
     assert _batch_create(L, 2, [0, 5, 9], arr) == L.BTREE_EINVAL  # mixed timing flag
+    arr = (L.Params * 2)(L.params(), L.params(exclude_self=True))
+    assert _batch_create(L, 2, [0, 5, 9], arr) == L.BTREE_EINVAL  # mixed exclude_self
+    assert "exclude_self" in L.last_error()
 
 
 def test_batch_null_handle(L):
