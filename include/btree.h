@@ -170,6 +170,48 @@ btree_status btree_find_neighbors(btree_handle t, const double* h,
                                   int32_t* nbrs, int64_t capacity,
                                   int64_t* total, void* hip_stream);
 
+/* Fused SPH consumer: the density sum over each particle's neighbours,
+ * computed inside the search with no list written (Section 4.7 uses the
+ * search inside an SPH code; the paper fixes no kernel W, this one is the
+ * cubic spline of support 2h):
+ *     rho[i] = (sum over the j that row i would list of m_j w(r_ij / h_i))
+ *              / (pi h_i^3),   rho[i] = 0 for an empty row,
+ *     w(q) = (1 - 1.5 q^2) + 0.75 q^3 (q < 1), 0.25 (2 - q)^3 (1 <= q < 2),
+ *     r_ij = sqrt((dx*dx + dy*dy) + dz*dz) from the FP64 coordinates,
+ * the neighbour set exactly that of btree_find_neighbors (exclude_self
+ * included).  Each term is rounded in a fixed order; terms are added in
+ * ascending j per part of the row and the parts in a fixed order, so a
+ * result is reproducible run to run and differs from a strictly sequential
+ * sum by rounding only.
+ * h: device FP64[n] (finite, >= 0); mass: device FP64[n] (original order) or
+ * NULL for unit masses; rho: device FP64[n] (written); counts: device
+ * int32[n] (written: row lengths) or NULL.  Synchronises the stream.
+ * Errors: EINVAL (NULL h/rho with n > 0, bad h: nothing written), ESTATE,
+ * ENOMEM, EDEVICE. */
+btree_status btree_density(btree_handle t, const double* h, const double* mass,
+                           double* rho, int32_t* counts, void* hip_stream);
+
+/* Smoothing lengths adapted to a target neighbour count (the target
+ * neighbours per particle of Table 3), on the handle's tree (h is an input
+ * of the search, not of the tree).  Every particle repeats, independently:
+ * c = its row length at its h (as btree_find_neighbors counts it); if
+ * |c - target| <= tol it is done; else its h becomes the low end of its
+ * bracket (c < target) or the high end (c > target), and h <- h f with
+ * f = min(2, (5c + target) / (6c)) (f = 2 for c = 0), or the bracket's
+ * midpoint (lo + hi) * 0.5 when h f would leave the bracket; each
+ * operation rounded once.  Stops when every particle is done or after
+ * max_iter rounds.
+ * h: device FP64[n], read and overwritten; counts: device int32[n] or NULL,
+ * receives the row lengths at the final h; iterations: host int32 or NULL,
+ * receives the number of update rounds made.  A particle with h = 0
+ * keeps it (its row stays empty).  Synchronises the stream once per
+ * round.  Errors: EINVAL (target not finite and > 0, tol not finite and
+ * >= 0, max_iter outside [0, 1000], NULL h, bad h values), ESTATE, ENOMEM,
+ * EDEVICE. */
+btree_status btree_adapt_h(btree_handle t, double* h, double target, double tol,
+                           int32_t max_iter, int32_t* counts, int32_t* iterations,
+                           void* hip_stream);
+
 /* Tree shape and last-search counters.  Errors: EINVAL (NULL argument). */
 btree_status btree_stats(btree_handle t, btree_stats_t* out);
 

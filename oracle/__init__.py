@@ -19,6 +19,14 @@ The arithmetic lives in ``oracle.c`` (plain C, FP64, no FMA contraction):
   (b = 2 at every split) the paper compares against.
 * ``eq1_branching``, ``eq2_subcell``, ``eq3_cell_id``, ``eq5_range``: the
   equations of Section 3, one function each.
+* ``sph_shape`` / ``density``: the SPH density sum over each row (the use of
+  the search inside an SPH code, Section 4.7; cubic-spline kernel of
+  support 2h, since the paper fixes none), terms added in ascending j.
+* ``adapt_h``: smoothing lengths driven to a target neighbour count (the
+  target of Table 3): each particle repeats c = its count at h, and while
+  |c - T| > tol records h as the low (c < T) or high end of a bracket and
+  takes h min(2, (5c + T) / (6c)) (2 when c = 0), or the bracket's midpoint
+  if that leaves the bracket.
 
 Parity is pinned by tests/test_oracle.py against closed forms, the paper's
 worked examples, invariants and an independent k-d tree (scipy).
@@ -79,6 +87,10 @@ def _load():
                                           P, P, I64, P, P, I64, P, P, P, I64, P]
         lib.oracle_cell_lists.restype = I64
         lib.oracle_cell_lists.argtypes = [P, P, P, P, I64, P, P, P, I64]
+        lib.oracle_sph_shape.restype = D
+        lib.oracle_sph_shape.argtypes = [D, D]
+        lib.oracle_density.restype = I64
+        lib.oracle_density.argtypes = [P, P, P, P, P, I64, ctypes.c_int32, P, P]
         lib.oracle_cell_check.restype = I64
         lib.oracle_cell_check.argtypes = [P, P, P, P, I64, P, P, P, P, I64]
         _lib = lib
@@ -183,6 +195,80 @@ def cell_check(x, y, z, h, counts, offsets, nbrs, max_bad: int = 64):
     if k < 0:
         raise MemoryError("oracle cell check: out of memory")
     return int(k), np.sort(bad[:min(k, max_bad)])
+
+
+def cell_counts(x, y, z, h) -> np.ndarray:
+    """Row lengths of all rows by the cell list (int64)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.shape[0]
+    c = np.empty(max(n, 1), dtype=np.int64)
+    o = np.empty(n + 1, dtype=np.int64)
+    if _load().oracle_cell_lists(_ptr(x), _ptr(y), _ptr(z), _ptr(h), n, _ptr(c), _ptr(o),
+                                 None, 0) < 0:
+        raise MemoryError("oracle cell list: out of memory")
+    return c[:n]
+
+
+def sph_shape(d2: float, h: float) -> float:
+    """Cubic-spline shape w(sqrt(d2) / h); W = w / (pi h^3)."""
+    return float(_load().oracle_sph_shape(float(d2), float(h)))
+
+
+def density(x, y, z, h, mass=None, exclude_self=False):
+    """SPH density of every particle over its row: (rho float64, counts int64)."""
+    x, y, z, h = map(_f64, (x, y, z, h))
+    n = x.shape[0]
+    m = None if mass is None else _f64(mass)
+    rho = np.empty(max(n, 1), dtype=np.float64)
+    c = np.empty(max(n, 1), dtype=np.int64)
+    if _load().oracle_density(_ptr(x), _ptr(y), _ptr(z), _ptr(h),
+                              _ptr(m) if m is not None else None, n,
+                              1 if exclude_self else 0, _ptr(rho), _ptr(c)) < 0:
+        raise MemoryError("oracle density: out of memory")
+    return rho[:n], c[:n]
+
+
+def adapt_h(x, y, z, h, target, tol=0.0, max_iter=50, exclude_self=False):
+    """Smoothing lengths driven to a target count.  Every particle, on its
+    own: c = its row length at its h; if |c - target| <= tol it is done;
+    else h is recorded as the low end (c < target) or high end (c > target)
+    of the particle's bracket (initially 0 and +inf) and replaced by
+    h f, f = min(2, (5c + target) / (6c)) (f = 2 when c = 0), or by the
+    bracket's midpoint (lo + hi) * 0.5 when h f is not strictly inside the
+    bracket; one rounding per operation.  Rounds stop when no h changes or
+    after max_iter.  A particle with h = 0 keeps it.  Returns (h, counts at
+    the final h, rounds made)."""
+    h = _f64(h).copy()
+    T = float(target)
+    lo = np.zeros_like(h)
+    hi = np.full_like(h, np.inf)
+
+    def count(hh):
+        c = cell_counts(x, y, z, hh)
+        if exclude_self:
+            c = c - ((2.0 * hh) * (2.0 * hh) > 0.0)
+        return c.astype(np.float64)
+
+    c = count(h)
+    it = 0
+    while it < max_iter:
+        off = (np.abs(c - T) > tol) & (h != 0.0)  # h = 0 cannot move
+        if not off.any():
+            break
+        cc, hv, lb, ub = c[off], h[off], lo[off], hi[off]
+        below = cc < T
+        lb = np.where(below, hv, lb)
+        ub = np.where(below, ub, hv)
+        f = np.full(cc.shape, 2.0)
+        pos = cc > 0.0
+        f[pos] = np.minimum(2.0, (5.0 * cc[pos] + T) / (6.0 * cc[pos]))
+        p = hv * f
+        out = (p >= ub) | (p <= lb)
+        p = np.where(out, (lb + ub) * 0.5, p)
+        h[off], lo[off], hi[off] = p, lb, ub
+        it += 1
+        c = count(h)
+    return h, c.astype(np.int64), it
 
 
 def eq1_branching(n: int, s: int) -> int:

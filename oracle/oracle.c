@@ -35,6 +35,16 @@
  *     the octree option every split uses b = 2 (the octree the paper
  *     compares against; Section 3.1 Step 3 reaches it when b halves to 2).
  *
+ *  3. Two uses of the lists inside an SPH step, each a plain definition
+ *     over the rows of part 1:
+ *      - the density sum (SPH use of the search, Section 4.7; the paper fixes
+ *        no kernel, this is the cubic spline of support 2h):
+ *          rho_i = (sum_{j in N(i), ascending} m_j w(r_ij / h_i)) / (pi h_i^3),
+ *          w(q) = (1 - 1.5 q^2) + 0.75 q^3 for q < 1, 0.25 (2 - q)^3 for
+ *          1 <= q < 2, r_ij = sqrt(d2) with d2 as in P64, 0 for empty rows;
+ *      - smoothing lengths adapted to a target neighbour count (the target
+ *        of Table 3), in oracle/__init__.py on the counts of part 1.
+ *
  * Readings where the paper is silent or inconsistent (each also listed in
  * the design notes):
  *   - distance test is strict (<), as the text says; Algorithm 2 prints <=;
@@ -453,6 +463,73 @@ int64_t oracle_cell_check(const double *x, const double *y, const double *z,
     }
     cl_free(&G);
     return err ? -2 : nbad;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Part 1c: the SPH density over the rows                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Cubic spline shape w(q), q = r / h, from the squared distance d2:
+ * r = sqrt(d2), q = r / h; w = (1 - 1.5 q^2) + 0.75 q^3 (q < 1),
+ * 0.25 ((2 - q)^2 (2 - q)) (1 <= q < 2), 0 beyond.  W(r, h) = w / (pi h^3)
+ * integrates to 1 over space. */
+double oracle_sph_shape(double d2, double h)
+{
+    double r = sqrt(d2);
+    double q = r / h;
+    if (q < 1.0) {
+        double q2 = q * q;
+        double q3 = q2 * q;
+        return (1.0 - 1.5 * q2) + 0.75 * q3;
+    }
+    if (q < 2.0) {
+        double t = 2.0 - q;
+        return 0.25 * ((t * t) * t);
+    }
+    return 0.0;
+}
+
+/* rho[i] = (sum over row i of N, ascending j, of m_j w(r_ij / h_i))
+ * / (pi h_i^3), 0 for an empty row; mass NULL = unit masses; exclude_self
+ * drops j = i from every row.  counts[i] (if not NULL) = the row length.
+ * Rows from the cell list (part 1b).  Returns 0, or -2 when out of memory. */
+int64_t oracle_density(const double *x, const double *y, const double *z,
+                       const double *h, const double *mass, int64_t n,
+                       int32_t exclude_self, double *rho, int64_t *counts)
+{
+    cl_grid G;
+    if (cl_build(&G, x, y, z, h, n)) { cl_free(&G); return -2; }
+    int err = 0;
+    #pragma omp parallel
+    {
+        int32_t *buf = NULL;
+        int64_t bcap = 0;
+        #pragma omp for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; ++i) {
+            int64_t m = cl_row(&G, i, &buf, &bcap);
+            if (m < 0) {
+                #pragma omp atomic write
+                err = 1;
+                continue;
+            }
+            double sum = 0.0;
+            int64_t c = 0;
+            for (int64_t k = 0; k < m; ++k) {
+                int32_t j = buf[k];
+                if (exclude_self && j == i) continue;
+                double dx = x[i] - x[j], dy = y[i] - y[j], dz = z[i] - z[j];
+                double d2 = (dx * dx + dy * dy) + dz * dz;
+                double w = oracle_sph_shape(d2, h[i]);
+                sum += mass ? mass[j] * w : w;
+                ++c;
+            }
+            rho[i] = c == 0 ? 0.0 : sum / (3.141592653589793 * ((h[i] * h[i]) * h[i]));
+            if (counts) counts[i] = c;
+        }
+        free(buf);
+    }
+    cl_free(&G);
+    return err ? -2 : 0;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -31,7 +31,7 @@ SYMBOLS = ["btree_params_default", "btree_build", "btree_rebuild", "btree_find_n
            "btree_stats", "btree_export", "btree_destroy", "btree_last_error",
            "btree_batch_create", "btree_batch_run", "btree_batch_stats", "btree_batch_destroy",
            "btree_batch_graph_counts", "btree_tune_space_default", "btree_tune",
-           "btree_find_neighbors_noalloc"]
+           "btree_find_neighbors_noalloc", "btree_density", "btree_adapt_h"]
 
 NOALLOC_MAX_N = 65536
 
@@ -103,6 +103,11 @@ def lib():
         L.btree_batch_destroy.argtypes = [P]
         L.btree_batch_graph_counts.restype = ctypes.c_int
         L.btree_batch_graph_counts.argtypes = [P, ctypes.POINTER(I64), ctypes.POINTER(I64)]
+        L.btree_density.restype = ctypes.c_int
+        L.btree_density.argtypes = [P, P, P, P, P, P]
+        L.btree_adapt_h.restype = ctypes.c_int
+        L.btree_adapt_h.argtypes = [P, P, ctypes.c_double, ctypes.c_double, ctypes.c_int32, P,
+                                    ctypes.POINTER(ctypes.c_int32), P]
         L.btree_find_neighbors_noalloc.restype = ctypes.c_int
         L.btree_find_neighbors_noalloc.argtypes = [P, P, P, P, I64, ctypes.POINTER(Params), P,
                                                    P, P, I64, ctypes.POINTER(I64), P]
@@ -244,6 +249,41 @@ class BTree:
         nbrs = torch.empty(max(total, 1), dtype=torch.int32, device=self.device)
         self.fill(h, counts, offsets, nbrs, stream=stream)
         return counts, offsets, nbrs[:total]
+
+    def density(self, h, mass=None, rho=None, counts=None, stream=None):
+        """Fused SPH density (btree_density): (rho float64[n], counts int32[n])."""
+        import torch
+        h = _dev_f64(h, "h")
+        if h.shape[0] != self.n:
+            raise ValueError("h must have n entries")
+        if mass is not None:
+            mass = _dev_f64(mass, "mass")
+            if mass.shape[0] != self.n:
+                raise ValueError("mass must have n entries")
+        if rho is None:
+            rho = torch.empty(self.n, dtype=torch.float64, device=self.device)
+        if counts is None:
+            counts = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        _check(lib().btree_density(self._h, ctypes.c_void_p(h.data_ptr()),
+                                   ctypes.c_void_p(mass.data_ptr()) if mass is not None else None,
+                                   ctypes.c_void_p(rho.data_ptr()),
+                                   ctypes.c_void_p(counts.data_ptr()), _stream(stream)))
+        return rho, counts
+
+    def adapt_h(self, h, target, tol=0.0, max_iter=50, counts=None, stream=None):
+        """btree_adapt_h: adapts h (device float64[n], overwritten) to the
+        target count; returns (counts at the final h, update rounds)."""
+        import torch
+        h = _dev_f64(h, "h")
+        if h.shape[0] != self.n:
+            raise ValueError("h must have n entries")
+        if counts is None:
+            counts = torch.empty(self.n, dtype=torch.int32, device=self.device)
+        it = ctypes.c_int32()
+        _check(lib().btree_adapt_h(self._h, ctypes.c_void_p(h.data_ptr()), float(target),
+                                   float(tol), int(max_iter), ctypes.c_void_p(counts.data_ptr()),
+                                   ctypes.byref(it), _stream(stream)))
+        return counts, int(it.value)
 
     def stats(self) -> dict:
         s = Stats()

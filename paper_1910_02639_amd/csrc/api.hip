@@ -239,6 +239,62 @@ btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* coun
     });
 }
 
+btree_status btree_density(btree_handle H, const double* h, const double* mass, double* rho,
+                           int32_t* counts, void* hip_stream) {
+    return guarded([&] {
+        if (!H) fail(BTREE_ESTATE, "btree_density: NULL handle");
+        Tree* t = &H->t;
+        if (!t->valid) fail(BTREE_ESTATE, "btree_density: the handle holds no tree");
+        if (t->n > 0 && (!h || !rho)) fail(BTREE_EINVAL, "btree_density: NULL h or rho");
+        if (t->n == 0) {
+            set_error("");
+            return;
+        }
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        if (!counts) {
+            t->aux_counts.reserve(sizeof(int32_t) * (size_t)t->n);
+            counts = t->aux_counts.as<int32_t>();
+        }
+        t->p1_total = -1;  // a later pass 2 needs its own pass 1
+        find_no_rows(*t, h, counts, mass, rho, st);
+        set_error("");
+    });
+}
+
+btree_status btree_adapt_h(btree_handle H, double* h, double target, double tol, int32_t max_iter,
+                           int32_t* counts, int32_t* iterations, void* hip_stream) {
+    return guarded([&] {
+        if (!H) fail(BTREE_ESTATE, "btree_adapt_h: NULL handle");
+        Tree* t = &H->t;
+        if (!t->valid) fail(BTREE_ESTATE, "btree_adapt_h: the handle holds no tree");
+        if (t->n > 0 && !h) fail(BTREE_EINVAL, "btree_adapt_h: NULL h");
+        if (!std::isfinite(target) || !(target > 0.0))
+            fail(BTREE_EINVAL, "btree_adapt_h: target must be finite and > 0");
+        if (!std::isfinite(tol) || tol < 0.0) fail(BTREE_EINVAL, "btree_adapt_h: tol must be finite and >= 0");
+        if (max_iter < 0 || max_iter > 1000) fail(BTREE_EINVAL, "btree_adapt_h: max_iter must be in [0, 1000]");
+        if (iterations) *iterations = 0;
+        if (t->n == 0) {
+            set_error("");
+            return;
+        }
+        hipStream_t st = static_cast<hipStream_t>(hip_stream);
+        if (!counts) {
+            t->aux_counts.reserve(sizeof(int32_t) * (size_t)t->n);
+            counts = t->aux_counts.as<int32_t>();
+        }
+        t->p1_total = -1;
+        adapt_h_begin(*t, st);
+        find_no_rows(*t, h, counts, nullptr, nullptr, st);
+        int32_t it = 0;
+        while (it < max_iter && adapt_h_step(*t, h, counts, target, tol, st) > 0) {
+            ++it;
+            find_no_rows(*t, h, counts, nullptr, nullptr, st);
+        }
+        if (iterations) *iterations = it;
+        set_error("");
+    });
+}
+
 btree_status btree_stats(btree_handle H, btree_stats_t* out) {
     if (!H || !out) {
         set_error("btree_stats: NULL argument");

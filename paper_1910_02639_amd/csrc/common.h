@@ -240,7 +240,7 @@ struct Ctl {
     uint32_t nbtasks;           // exhaustive count-pass tasks (unit x span of its set)
     int64_t bspan;              // candidates per exhaustive count-pass task
     int32_t bfill_tasks;        // 1: the exhaustive fill pass also runs by tasks
-    int32_t pad_ctl;
+    uint32_t nadapt;            // h adaptation: particles whose h changed (atomic)
 };
 
 // Allocation from the search's pools (row scratch, walk lists) goes through
@@ -341,6 +341,8 @@ struct Tree {
     DBuf whdr;     // int4 per work item: walk result header
     DBuf ibox;     // per work item: box E and the FP32 filter's item-wide bounds (64 bytes)
     DBuf wl;       // int2 pool: candidate leaves (first particle, count) of every item
+    DBuf aux_counts;  // int32 per particle, when a caller passes no counts buffer
+    DBuf adapt_br;    // double2 per particle: bracket (lo, hi) of the h adaptation
     Work ws;
     Timer timer;
 
@@ -518,6 +520,16 @@ void find_reserve(Tree& t, int64_t entries);
 void grow_pools(Tree& t, int overflow);
 int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets,
                    hipStream_t st);
+// A search pass that writes counts (rho null) or counts and the fused SPH
+// densities (mass null: unit masses), no rows; synchronises the stream.
+void find_no_rows(Tree& t, const double* h, int32_t* counts, const double* mass, double* rho,
+                  hipStream_t st);
+// The h adaptation: brackets cleared, then one round per call on counts
+// taken at h (original order); a round returns how many h changed
+// (synchronises the stream).
+void adapt_h_begin(Tree& t, hipStream_t st);
+int64_t adapt_h_step(Tree& t, double* h, const int32_t* counts, double target, double tol,
+                     hipStream_t st);
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs,
                 hipStream_t st);
 

@@ -59,7 +59,7 @@ constexpr int kCMax = 1536;  // staged candidates per item (both forms)
 constexpr int kBuckets = 256;       // original-index buckets of the staged list
 constexpr int kBucketSortMax = 48;  // a fuller bucket sorts the whole item instead
 
-enum { kCount = 0, kFill = 1 };
+enum { kCount = 0, kFill = 1, kDens = 2 };  // exhaustive path: count, rows, density
 
 // The FP64 predicate of the method, every operation rounded.
 __device__ __forceinline__ bool p64(double xi, double yi, double zi, double R, double xj,
@@ -499,8 +499,58 @@ constexpr int kNoCount = kHuge + 1;  // overflow of the leaf list, candidates no
 // it when ci >= 0 and the list is whole and fits, else walk here.
 constexpr int kSubGroup = 8;  // queries per sub-item of a split work item
 
+// What a search pass writes per query: the row (to the scratch, placed
+// later), the count only (h adaptation), or the count and the fused SPH
+// density sum over the row (no row materialised).
+enum { kOutRows = 0, kOutCount = 1, kOutDensity = 2 };
+
+// Caller buffers of the density form: masses (original order; null = unit
+// masses) and the densities written.
+struct DensOut {
+    const double* mass;
+    double* rho;
+};
+
+// Shape of the cubic-spline SPH kernel (the M4 B-spline: support 2h,
+// W(r, h) = w(r / h) / (pi h^3)), evaluated from the squared distance of a
+// pair with every operation rounded in this order:
+//   r = sqrt(d2), q = r / h,
+//   q < 1: (1 - 1.5 q^2) + 0.75 q^3,  1 <= q < 2: 0.25 ((2 - q)^2 (2 - q)).
+__device__ __forceinline__ double sph_shape(double d2, double h) {
+    const double q = __ddiv_rn(__dsqrt_rn(d2), h);
+    if (q < 1.0) {
+        const double q2 = __dmul_rn(q, q);
+        return __dadd_rn(__dsub_rn(1.0, __dmul_rn(1.5, q2)), __dmul_rn(0.75, __dmul_rn(q2, q)));
+    }
+    if (q < 2.0) {
+        const double t = __dsub_rn(2.0, q);
+        return __dmul_rn(0.25, __dmul_rn(__dmul_rn(t, t), t));
+    }
+    return 0.0;
+}
+
+// m_j w(r_ij / h_i) of one neighbour j (key = its original index) of the
+// query at (x, y, z) with smoothing length h, from FP64 coordinates.
+__device__ __forceinline__ double sph_term(double x, double y, double z, double h, int key,
+                                           const double4* __restrict__ orig,
+                                           const double* __restrict__ mass) {
+    const double4 o = orig[key];
+    const double dx = __dsub_rn(x, o.x), dy = __dsub_rn(y, o.y), dz = __dsub_rn(z, o.z);
+    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+    const double w = sph_shape(d2, h);
+    return mass ? __dmul_rn(mass[key], w) : w;
+}
+
+// Density from the sum of the terms of a row: sum / (pi h^3); 0 for an
+// empty row.
+__device__ __forceinline__ double sph_density(double sum, int count, double h) {
+    if (count == 0) return 0.0;
+    return __ddiv_rn(sum, __dmul_rn(3.141592653589793, __dmul_rn(__dmul_rn(h, h), h)));
+}
+
 // SMALL: units of at most kSubGroup queries test with lane = candidate.
-template <bool F32, int WALK, int CMAX = kCMax, int LMAX = kLMax, bool SMALL = false>
+template <bool F32, int WALK, int CMAX = kCMax, int LMAX = kLMax, bool SMALL = false,
+          int OUT = kOutRows>
 __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                                           const int4* __restrict__ whdr,
                                           const int2* __restrict__ wl,
@@ -518,7 +568,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                                            int32_t* __restrict__ scratch, int64_t scap,
                                            unsigned long long* __restrict__ scur, int stripe,
                                            Ctl* __restrict__ ctl, Stats* __restrict__ stats,
-                                           const int excl) {
+                                           const int excl, const DensOut dout) {
     using E = typename Ent<F32>::T;
     constexpr int kMaxW = ((CMAX / kWaves) + 31) / 32;  // bit words per lane and wavefront
     __shared__ E s_cand[CMAX];
@@ -903,13 +953,32 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     for (int i = 0; i < kMaxW; ++i) wq[i] = 0u;
     int hits = 0;
     unsigned long long conf = 0;
+    // (Density form: per-query sums of the wavefront's part, in LDS.)
+    double* s_dens = nullptr;
+    if constexpr (OUT == kOutDensity) {
+        __shared__ double s_dens_mem[kWaves][64];
+        s_dens = &s_dens_mem[0][0];
+    }
     if (small) {
         if (lane >= ch.cnt) s_cnt[w][lane] = 0;
+        if (OUT == kOutDensity && lane >= ch.cnt) s_dens[w * 64 + lane] = 0.0;
         for (int q = 0; q < ch.cnt; ++q) {
             const Q Qd = query(q);
             int hq = 0;
-            for (int c = ch0; c < ch1; ++c) hq += __popcll(chunk_hits(Qd, c, conf));
+            double dq = 0.0;
+            for (int c = ch0; c < ch1; ++c) {
+                const uint64_t m = chunk_hits(Qd, c, conf);
+                hq += __popcll(m);
+                if constexpr (OUT == kOutDensity) {
+                    double term = 0.0;
+                    if ((m >> lane) & 1)
+                        term = sph_term(Qd.x, Qd.y, Qd.z, 0.5 * Qd.R,
+                                        Ent<F32>::key(cand(c * 64 + lane)), orig, dout.mass);
+                    dq += wave_sum(term);
+                }
+            }
             if (lane == 0) s_cnt[w][q] = hq;
+            if (OUT == kOutDensity && lane == 0) s_dens[w * 64 + q] = dq;
         }
     }
     for (int kw = k0; !small && kw < k1; kw += 32) {
@@ -1025,7 +1094,50 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     }
     if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
     if (!small) s_cnt[w][lane] = hits;
+    if constexpr (OUT == kOutDensity) {
+        // The lane's hits in its block, in ascending index.
+        if (!small) {
+            double acc = 0.0;
+            const int wbase = kMaxW - nw;
+#pragma unroll
+            for (int i = 0; i < kMaxW; ++i) {
+                const int wi = i - wbase;
+                if (wi >= 0 && qv) {
+                    uint32_t word = wq[i];
+                    const int kb = k0 + 32 * wi;
+                    while (word) {
+                        const int j = __clz(word);
+                        word &= ~(0x80000000u >> j);
+                        acc += sph_term(qp.x, qp.y, qp.z, 0.5 * R, Ent<F32>::key(cand(kb + j)),
+                                        orig, dout.mass);
+                    }
+                }
+            }
+            s_dens[w * 64 + lane] = acc;
+        }
+    }
     __syncthreads();
+    if constexpr (OUT != kOutRows) {
+        // Counts (and densities: the wavefronts' parts added in order); no
+        // rows.
+        if (w == 0) {
+            int c = 0;
+#pragma unroll
+            for (int k = 0; k < kWaves; ++k) c += s_cnt[k][lane];
+            if (qv) counts[qidx] = c;
+            if constexpr (OUT == kOutDensity) {
+                const double sum = ((s_dens[lane] + s_dens[64 + lane]) + s_dens[128 + lane]) +
+                                   s_dens[192 + lane];
+                if (qv) dout.rho[qidx] = sph_density(sum, c, 0.5 * R);
+            }
+            if (lane == 0) {
+                unsigned long long tests = (unsigned long long)C * (unsigned long long)ch.cnt;
+                atomicAdd(&stats->pair_tests, tests);
+                atomicAdd(&stats->candidates, (unsigned long long)C);
+            }
+        }
+        return 0;
+    }
 
     // Row lengths, then one scratch allocation for the item.
     if (w == 0) {
@@ -1136,7 +1248,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
 // with a margin and reports an item count above it as an overflow).  Items
 // whose candidates overflow the shared-memory budget are listed for
 // k_sweep_split.
-template <bool F32>
+template <bool F32, int OUT>
 __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                const double4* __restrict__ pos,
                                                const double4* __restrict__ orig,
@@ -1155,7 +1267,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                const int4* __restrict__ whdr,
                                                const int2* __restrict__ wl,
                                                const ItemBox* __restrict__ ibox,
-                                               Stats* __restrict__ stats, const int excl) {
+                                               Stats* __restrict__ stats, const int excl,
+                                               const DensOut dout) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     const int nch = ctl->n_chunks;
     const int ci = blockIdx.x;
@@ -1163,9 +1276,9 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
         atomicOr(&ctl->overflow, kOvfChunks);
     if (ci >= nch) return;
     const Chunk ch = chunks[ci];
-    const int C = sweep_item<F32, 1>(ci, ch, whdr, wl, ibox, pos, orig, nodes, ctab, leaves, lrange,
-                                        sets, h, counts, soff, scratch, scap, scur,
-                                        stripe_of(ch.beg), ctl, stats, excl);
+    const int C = sweep_item<F32, 1, kCMax, kLMax, false, OUT>(
+        ci, ch, whdr, wl, ibox, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
+        scratch, scap, scur, stripe_of(ch.beg), ctl, stats, excl, dout);
     if (C && threadIdx.x == 0) {
         const uint32_t k = atomicAdd(&ctl->nsplit, 1u);
         split[k] = Chunk{ch.beg, ch.cnt, ch.set, C};
@@ -1207,7 +1320,7 @@ __device__ __forceinline__ void to_brute(const Chunk q, const double4* __restric
 // would be long, so units there go down to single queries first.
 constexpr int64_t kDenseSet = 32768;
 
-template <bool F32, int LEVEL>
+template <bool F32, int LEVEL, int OUT>
 __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ in,
                                                      Chunk* __restrict__ next,
                                                      const int32_t* __restrict__ split_ci,
@@ -1229,7 +1342,8 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
                                                      Ctl* __restrict__ ctl,
                                                      Chunk* __restrict__ brute,
                                                      int32_t* __restrict__ bcnt,
-                                                     Stats* __restrict__ stats, const int excl) {
+                                                     Stats* __restrict__ stats, const int excl,
+                                                     const DensOut dout) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     // Units of this level: level 1 takes each listed item whole; levels 2
     // and 3 cut each listed unit into parts of kSubGroup queries or of one.
@@ -1258,9 +1372,10 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         }
         // Level 1 takes the item whole: its walk list, if whole, still holds.
         const int ci = LEVEL == 1 ? split_ci[u] : -1;
-        const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2)>(
+        const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2), OUT>(
             ci, unit, whdr, wl, LEVEL == 1 ? ibox : nullptr, pos, orig, nodes, ctab, leaves, lrange,
-            sets, h, counts, soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats, excl);
+            sets, h, counts, soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats, excl,
+            dout);
         if (!C) continue;
         __syncthreads();
         if (LEVEL == 3 || (nset <= kDenseSet && C != kNoCount && 4 * (int64_t)C > nset)) {
@@ -1456,7 +1571,8 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
                                                int32_t* __restrict__ counts,
                                                const int64_t* __restrict__ offsets, int64_t n,
                                                int64_t capacity, int32_t* __restrict__ nbrs,
-                                               Ctl* __restrict__ ctl, const int excl) {
+                                               Ctl* __restrict__ ctl, const int excl,
+                                               const DensOut dout) {
     __shared__ double4 s_c[kDenseTile];
     __shared__ int32_t s_cnt[kWaves][64];
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
@@ -1465,7 +1581,9 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
     const int32_t* off = bset + 2 * nsets;
     const int32_t* uoff = off + nsets + 1;
     const int32_t* toff = uoff + nsets + 1;
-    const bool by_task = MODE == kCount || ctl->bfill_tasks;
+    // The density form takes each unit whole (one workgroup adds all of a
+    // query's terms, in a fixed order).
+    const bool by_task = MODE == kCount || (MODE == kFill && ctl->bfill_tasks);
     const int32_t* woff = by_task ? toff : uoff;  // first task / unit of each set
     const uint32_t nwork = by_task ? ctl->nbtasks : ctl->nbunits;
     const int t = threadIdx.x, lane = t & 63;
@@ -1498,6 +1616,7 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
         if (MODE == kFill && by_task && qv)
             for (int64_t k = 0; k < ks; ++k) run += btab[((int64_t)u - ks + k) * 64 + lane];
         int64_t hits = 0;
+        double dsum = 0.0;  // density form: this lane's terms, tile by tile
         for (int64_t t0 = c0; t0 < c1; t0 += kDenseTile) {
             __syncthreads();  // the previous tile is no longer read
             for (int i = t; i < kDenseTile; i += kWG) {
@@ -1533,8 +1652,21 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
                 wd[b] = word;
                 mine += __popc(word);
             }
-            if (MODE == kCount) {
+            if (MODE == kCount || MODE == kDens) {
                 hits += mine;
+                if (MODE == kDens && qv) {
+#pragma unroll
+                    for (int b = 0; b < kDenseWords; ++b) {
+                        uint32_t word = wd[b];
+                        const int k0 = w * (kDenseTile / kWaves) + 32 * b;
+                        while (word) {
+                            const int j = __clz(word);
+                            word &= ~(0x80000000u >> j);
+                            dsum += sph_term(qp.x, qp.y, qp.z, 0.5 * R,
+                                             (int)(jb + t0 + k0 + j), orig, dout.mass);
+                        }
+                    }
+                }
             } else {
                 s_cnt[w][lane] = mine;
                 __syncthreads();
@@ -1571,6 +1703,19 @@ __global__ __launch_bounds__(kWG) void k_dense(const int32_t* __restrict__ bq,
                 if (ctl->bfill_tasks) btab[(int64_t)u * 64 + lane] = qv ? tot : 0;
             }
         }
+        if constexpr (MODE == kDens) {
+            __shared__ double s_ds[kWaves][64];
+            __syncthreads();
+            s_cnt[w][lane] = (int)hits;
+            s_ds[w][lane] = dsum;
+            __syncthreads();
+            if (w == 0 && qv) {
+                const int tot = s_cnt[0][lane] + s_cnt[1][lane] + s_cnt[2][lane] + s_cnt[3][lane];
+                counts[qidx] = tot;
+                const double sum = ((s_ds[0][lane] + s_ds[1][lane]) + s_ds[2][lane]) + s_ds[3][lane];
+                dout.rho[qidx] = sph_density(sum, tot, 0.5 * R);
+            }
+        }
         __syncthreads();
     }
 }
@@ -1589,6 +1734,7 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
         ctl->nbrute = 0;
         ctl->nbunits = 0;
         ctl->nbtasks = 0;
+        ctl->nadapt = 0;
         ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
         ctl->overflow &= ~(kOvfScratch | kOvfCapacity | kOvfChunks | kOvfWalk);
         stats->pair_tests = 0;
@@ -1597,6 +1743,46 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
         stats->candidates = 0;
         stats->split = 0;
     }
+}
+
+// Brackets of the h adaptation: lo = 0 and hi = +inf (none known yet).
+__global__ void k_adapt_init(double2* __restrict__ br, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        br[i] = make_double2(0.0, INFINITY);
+}
+
+// One round of the h adaptation (original order).  A particle with h > 0
+// whose count c is off the target T by more than tol records its h as the
+// lower (c < T) or upper (c > T) end of its bracket, and proposes h f with
+// f = min(2, (5c + T) / (6c)) (2 when c = 0): half the first-order step
+// towards (T / c)^(1/3) around c = T.  A proposal that leaves the bracket
+// is replaced by the bracket's midpoint, so a particle whose band
+// [T - tol, T + tol] is reachable cannot cycle.  Basic operations only,
+// each rounded once, so every platform takes the same steps.
+__global__ void k_adapt_h(const int32_t* __restrict__ counts, double* __restrict__ h,
+                          double2* __restrict__ br, int64_t n, double target, double tol,
+                          Ctl* __restrict__ ctl) {
+    unsigned mine = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double c = (double)counts[i];
+        const double hv = h[i];
+        if (fabs(__dsub_rn(c, target)) <= tol || hv == 0.0) continue;  // done, or cannot move
+        double2 b = br[i];
+        if (c < target) b.x = hv;
+        else b.y = hv;
+        double f = 2.0;
+        if (c > 0.0)
+            f = fmin(2.0, __ddiv_rn(__dadd_rn(__dmul_rn(5.0, c), target), __dmul_rn(6.0, c)));
+        double p = __dmul_rn(hv, f);
+        if (p >= b.y || p <= b.x) p = __dmul_rn(__dadd_rn(b.x, b.y), 0.5);
+        h[i] = p;
+        br[i] = b;
+        ++mine;
+    }
+    mine = wave_sum(mine);
+    if (lane_id() == 0 && mine) atomicAdd(&ctl->nadapt, mine);
 }
 
 // Lists per set: totals[k] = offsets[end of set k] - offsets[start of set k].
@@ -1610,41 +1796,72 @@ constexpr unsigned kBruteGrid = 512;
 constexpr int64_t kWalkPerItem = 64;  // mean leaf entries per item the walk pool holds
 constexpr unsigned kSplitGrid = 1024;
 
-template <bool F32>
-void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep<F32>), dim3(grid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
+template <bool F32, int OUT>
+void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, DensOut dout,
+                  hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep<F32, OUT>), dim3(grid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.split_ci.as<int32_t>(),
                        t.whdr.as<int4>(), t.wl.as<int2>(), t.ibox.as<ItemBox>(),
-                       t.stats.as<Stats>(), t.prm.exclude_self);
+                       t.stats.as<Stats>(), t.prm.exclude_self, dout);
     BT_LAUNCH();
 }
 
-template <bool F32, int LEVEL>
+template <bool F32, int LEVEL, int OUT>
 void launch_split_level(Tree& t, const double* h, int32_t* counts, const Chunk* in, Chunk* next,
-                        hipStream_t st) {
-    hipLaunchKernelGGL((k_sweep_split<F32, LEVEL>), dim3(kSplitGrid), dim3(kWG), 0, st, in, next,
-                       t.split_ci.as<int32_t>(), t.whdr.as<int4>(), t.wl.as<int2>(),
+                        DensOut dout, hipStream_t st) {
+    hipLaunchKernelGGL((k_sweep_split<F32, LEVEL, OUT>), dim3(kSplitGrid), dim3(kWG), 0, st, in,
+                       next, t.split_ci.as<int32_t>(), t.whdr.as<int4>(), t.wl.as<int2>(),
                        t.ibox.as<ItemBox>(), t.pos.as<double4>(), t.orig.as<double4>(),
                        t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
                        t.sets.as<SetDev>(), t.hs.as<double>(), counts, t.soff.as<int64_t>(),
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.blist.as<Chunk>(), t.bset.as<int32_t>(),
-                       t.stats.as<Stats>(), t.prm.exclude_self);
+                       t.stats.as<Stats>(), t.prm.exclude_self, dout);
     BT_LAUNCH();
 }
 
-template <bool F32>
-void launch_split(Tree& t, const double* h, int32_t* counts, hipStream_t st) {
+template <bool F32, int OUT>
+void launch_split(Tree& t, const double* h, int32_t* counts, DensOut dout, hipStream_t st) {
     Chunk* l1 = t.split.as<Chunk>();
     Chunk* l2 = l1 + t.leaf_cap;
     Chunk* l3 = l2 + t.leaf_cap;
-    launch_split_level<F32, 1>(t, h, counts, l1, l2, st);
-    launch_split_level<F32, 2>(t, h, counts, l2, l3, st);
-    launch_split_level<F32, 3>(t, h, counts, l3, nullptr, st);
+    launch_split_level<F32, 1, OUT>(t, h, counts, l1, l2, dout, st);
+    launch_split_level<F32, 2, OUT>(t, h, counts, l2, l3, dout, st);
+    launch_split_level<F32, 3, OUT>(t, h, counts, l3, nullptr, dout, st);
+}
+
+template <int MODE>
+void launch_dense(Tree& t, int32_t* counts, const int64_t* offsets, int64_t capacity,
+                  int32_t* nbrs, DensOut dout, hipStream_t st) {
+    hipLaunchKernelGGL((k_dense<MODE>), dim3(kBruteGrid), dim3(kWG), 0, st, t.bq.as<int32_t>(),
+                       t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
+                       t.sets.as<SetDev>(), t.pos.as<double4>(), t.orig.as<double4>(),
+                       t.hs.as<double>(), counts, offsets, t.n, capacity, nbrs, t.ctl.as<Ctl>(),
+                       t.prm.exclude_self, dout);
+    BT_LAUNCH();
+}
+
+// Split levels and the exhaustive path's plan, regrouping and sweep of one
+// search pass (OUT: what it writes).
+template <int OUT>
+void counts_tail(Tree& t, const double* h, int32_t* counts, DensOut dout, hipStream_t st) {
+    if (t.prm.precision == BTREE_FP32_FILTER) launch_split<true, OUT>(t, h, counts, dout, st);
+    else launch_split<false, OUT>(t, h, counts, dout, st);
+    hipLaunchKernelGGL(k_brute_plan, dim3(1), dim3(kWG), 0, st, t.bset.as<int32_t>(),
+                       (int)t.nsets, t.sets.as<SetDev>(), t.ctl.as<Ctl>());
+    BT_LAUNCH();
+    hipLaunchKernelGGL(k_brute_group, dim3(kBruteGrid), dim3(kWG), 0, st, t.blist.as<Chunk>(),
+                       t.ctl.as<Ctl>(), t.bset.as<int32_t>(), (int)t.nsets, t.bq.as<int32_t>(),
+                       t.pos.as<double4>(), counts);
+    BT_LAUNCH();
+    if (OUT == kOutDensity)
+        launch_dense<kDens>(t, counts, nullptr, 0, nullptr, dout, st);
+    else
+        launch_dense<kCount>(t, counts, nullptr, 0, nullptr, dout, st);
 }
 
 }  // namespace
@@ -1694,27 +1911,46 @@ void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st) {
 
 void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStream_t st) {
     const unsigned g = (unsigned)std::max<int64_t>(1, grid);
-    if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true>(t, h, counts, g, st);
-    else launch_sweep<false>(t, h, counts, g, st);
+    const DensOut none{nullptr, nullptr};
+    if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true, kOutRows>(t, h, counts, g, none, st);
+    else launch_sweep<false, kOutRows>(t, h, counts, g, none, st);
 }
 
 void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
-    if (t.prm.precision == BTREE_FP32_FILTER) launch_split<true>(t, h, counts, st);
-    else launch_split<false>(t, h, counts, st);
-    hipLaunchKernelGGL(k_brute_plan, dim3(1), dim3(kWG), 0, st, t.bset.as<int32_t>(),
-                       (int)t.nsets, t.sets.as<SetDev>(), t.ctl.as<Ctl>());
-    BT_LAUNCH();
-    hipLaunchKernelGGL(k_brute_group, dim3(kBruteGrid), dim3(kWG), 0, st, t.blist.as<Chunk>(),
-                       t.ctl.as<Ctl>(), t.bset.as<int32_t>(), (int)t.nsets, t.bq.as<int32_t>(),
-                       t.pos.as<double4>(), counts);
-    BT_LAUNCH();
-    hipLaunchKernelGGL((k_dense<kCount>), dim3(kBruteGrid), dim3(kWG), 0, st,
-                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
-                       t.sets.as<SetDev>(), t.pos.as<double4>(),
-                       t.orig.as<double4>(), t.hs.as<double>(), counts, nullptr, t.n, (int64_t)0, nullptr,
-                       t.ctl.as<Ctl>(), t.prm.exclude_self);
-    BT_LAUNCH();
+    counts_tail<kOutRows>(t, h, counts, DensOut{nullptr, nullptr}, st);
     scan_exclusive_i32(counts, offsets, t.n, t, st, &t.ctl.as<Ctl>()->data_bad);
+}
+
+// A search pass that writes counts, or counts and densities, and no rows:
+// queued, then one host read of the control block for errors.  A walk-list
+// pool found too small is grown for the next pass (the items that did not
+// fit were searched by the split levels, so this pass is complete).
+void find_no_rows(Tree& t, const double* h, int32_t* counts, const double* mass, double* rho,
+                  hipStream_t st) {
+    find_reserve(t, std::max<int64_t>(t.scap, 1));
+    const DensOut d{mass, rho};
+    const unsigned g = (unsigned)std::max<int64_t>(1, t.n_chunks);
+    find_begin(t, h, st);
+    find_walk(t, h, t.n_chunks, st);
+    t.timer.start(kPhSweep, st);
+    if (rho) {
+        if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true, kOutDensity>(t, h, counts, g, d, st);
+        else launch_sweep<false, kOutDensity>(t, h, counts, g, d, st);
+    } else {
+        if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true, kOutCount>(t, h, counts, g, d, st);
+        else launch_sweep<false, kOutCount>(t, h, counts, g, d, st);
+    }
+    t.timer.stop(kPhSweep, st);
+    if (rho) counts_tail<kOutDensity>(t, h, counts, d, st);
+    else counts_tail<kOutCount>(t, h, counts, d, st);
+    BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
+    BT_HIP(hipMemcpyAsync(t.host_stripes, t.stripes.p, sizeof t.host_stripes,
+                          hipMemcpyDeviceToHost, st));
+    BT_HIP(hipStreamSynchronize(st));
+    if (t.host_ctl.data_bad & 2) fail(BTREE_EINVAL, "h must be finite and >= 0");
+    if (t.host_ctl.overflow & kOvfChunks) fail(BTREE_EDEVICE, "work items out of date");
+    if (t.host_ctl.overflow & kOvfWalk) grow_pools(t, kOvfWalk);
 }
 
 void find_place(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* nbrs,
@@ -1737,12 +1973,7 @@ void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* 
     // be null with a capacity of 0: nothing is written then).
     if (t.n > 0 && (!counts || !offsets))
         fail(BTREE_EDEVICE, "find_fill: counts or offsets missing");
-    hipLaunchKernelGGL((k_dense<kFill>), dim3(kBruteGrid), dim3(kWG), 0, st,
-                       t.bq.as<int32_t>(), t.bset.as<int32_t>(), (int)t.nsets, t.btab.as<int32_t>(),
-                       t.sets.as<SetDev>(), t.pos.as<double4>(), t.orig.as<double4>(),
-                       t.hs.as<double>(), nullptr, offsets, t.n, capacity, nbrs, t.ctl.as<Ctl>(),
-                       t.prm.exclude_self);
-    BT_LAUNCH();
+    launch_dense<kFill>(t, nullptr, offsets, capacity, nbrs, DensOut{nullptr, nullptr}, st);
     if (time_place) t.timer.start(kPhPlace, st);
     find_place(t, counts, offsets, nbrs, capacity, st);
     if (time_place) t.timer.stop(kPhPlace, st);
@@ -1795,6 +2026,24 @@ int64_t find_pass1(Tree& t, const double* h, int32_t* counts, int64_t* offsets, 
         grow_pools(t, t.host_ctl.overflow);
     }
     return total;
+}
+
+void adapt_h_begin(Tree& t, hipStream_t st) {
+    t.adapt_br.reserve(sizeof(double2) * (size_t)std::max<int64_t>(t.n, 1));
+    hipLaunchKernelGGL(k_adapt_init, dim3(std::min<unsigned>(grid_for(t.n, 256), 4096u)),
+                       dim3(256), 0, st, t.adapt_br.as<double2>(), t.n);
+    BT_LAUNCH();
+}
+
+int64_t adapt_h_step(Tree& t, double* h, const int32_t* counts, double target, double tol,
+                     hipStream_t st) {
+    hipLaunchKernelGGL(k_adapt_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 4096u)), dim3(256),
+                       0, st, counts, h, t.adapt_br.as<double2>(), t.n, target, tol,
+                       t.ctl.as<Ctl>());
+    BT_LAUNCH();
+    BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+    BT_HIP(hipStreamSynchronize(st));
+    return (int64_t)t.host_ctl.nadapt;
 }
 
 void find_pass2(Tree& t, const double* h, const int64_t* offsets, int32_t* nbrs, hipStream_t st) {
