@@ -131,7 +131,7 @@ def test_adapt_h_zero_rounds_and_errors():
     x, y, z, h = W.uniform_cube(5_000, 6, 64.0)
     dx, dy, dz, dh = to_dev(x, y, z, h)
     with btree.BTree(dx, dy, dz) as t:
-        c0, _ = t.density(dh)
+        _, c0 = t.density(dh)
         c, it = t.adapt_h(dh, 64, 1000, 10)  # every count within the tolerance
         assert it == 0 and torch.equal(c, c0)
         for bad in (dict(target=0.0), dict(target=float("nan")), dict(target=64, tol=-1.0),
