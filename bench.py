@@ -108,6 +108,19 @@ def hbm_measured(ph, workload):
     return out or None
 
 
+def roofline_hbm(n, total, kernel_ms, workload):
+    """The dominant kernel against the HBM roofline: the search's compulsory
+    bytes (coordinates 24 B, h 8 B, count 4 B, offset 8 B per particle, 4 B
+    per list entry) over the sweep kernel's time, with the measured traffic
+    (rocprofv3 counters, profiles/traffic.json) and its ratio to them."""
+    alg = n * (24 + 8 + 4 + 8) + 4 * total
+    gbs = alg / (kernel_ms * 1e-3) / 1e9
+    t = load_traffic("sweep_kernel", workload)
+    return {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "algorithmic_bytes": alg, "traffic": t,
+            "traffic_ratio": (t / alg) if t else None}
+
+
 def search_hbm(n, total, search_ms):
     # Compulsory HBM bytes of the whole search (both passes), per particle:
     # coordinates 24 B + h 8 B + count 4 B + offset 8 B, plus 4 B per entry.
@@ -172,6 +185,7 @@ def bench_single(name, precision, steps, warmup, compare, tuner, bucket=0):
                     "leaves": st["n_leaves"], "b_hist": st["b_hist"]},
            "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], ops,
                                 "k_sweep<%s>" % precision, name),
+           "roofline_hbm": roofline_hbm(n, total, ph["sweep_kernel"], name),
            "search_hbm": search_hbm(n, total, ph["pass1"] + ph["pass2"]),
            "hbm_measured": hbm_measured(ph, name) if precision == "fp32" else None}
     if compare and precision == "fp32":
@@ -283,8 +297,10 @@ def bench_batch(a, tuner):
         "tree": {"depth": st["depth"], "internal": st["n_internal"], "leaves": st["n_leaves"]},
         "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], OPS_PER_TEST_F32,
                              "k_sweep<fp32>", "Batch64"),
+        "roofline_hbm": roofline_hbm(n, total, ph["sweep_kernel"], "Batch64"),
         "search_hbm": search_hbm(n, total, ph["pass1"] + ph["pass2"]),
         "hbm_measured": hbm_measured(ph, "Batch64"),
+        "_prm32": prm32,
     }
     if not a.no_compare:
         k2 = max(2, min(a.steps, 5))
@@ -299,6 +315,147 @@ def bench_batch(a, tuner):
         out["batched_fp32_vs_fp64_per_set"] = out["value"] / f64["value"]
         out["batching_speedup_fp32"] = out["value"] / f32["value"]
     return out, sets
+
+
+# ---------------------------------------------------------------------------
+# b-tree against the octree, build-time sweeps, the fused density and the h
+# adaptation (single sets and the batch).
+# ---------------------------------------------------------------------------
+def _tree_view(st):
+    return {"depth": st["depth"], "internal": st["n_internal"], "leaves": st["n_leaves"]}
+
+
+def bench_octree_single(name, tuner, steps=5):
+    """The b-tree against the octree (b = 2 at every split) with the same
+    bucket size: BuildTree and FindNeighbors time per step, tree depths."""
+    import torch
+    from paper_1910_02639_amd import btree, workloads as W
+    x, y, z, h, _ = W.make(name)
+    n = len(x)
+    dx, dy, dz, dh = (torch.from_numpy(v).to("cuda:0") for v in (x, y, z, h))
+    prm = tuner.params_for(dx, dy, dz, dh, "fp32") or {"bucket_size": 64}
+    counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+    out = {"workload": name, "n": n, "bucket_size": prm["bucket_size"]}
+    for label, extra in (("btree", {}), ("octree", {"octree": True})):
+        log("octree comparison", name, label)
+        t = btree.BTree(dx, dy, dz, precision="fp32", timing=True, **prm, **extra)
+        _, _, total = t.count(dh, counts, offsets)
+        nbrs = torch.empty(max(total, 1), dtype=torch.int32, device="cuda:0")
+        el, ph, st = single_timed(t, (dx, dy, dz, dh, counts, offsets, nbrs), steps, 1)
+        t.close()
+        del nbrs
+        out[label] = {"build_ms": ph["build"], "search_ms": ph["pass1"] + ph["pass2"],
+                      "ms_per_step": 1e3 * el / steps,
+                      "pair_tests_per_particle": st["pair_tests"] / n, "tree": _tree_view(st)}
+    out["build_speedup_btree_vs_octree"] = out["octree"]["build_ms"] / out["btree"]["build_ms"]
+    out["search_speedup_btree_vs_octree"] = out["octree"]["search_ms"] / out["btree"]["search_ms"]
+    return out
+
+
+def bench_octree_batch(sets, prm32, steps=5):
+    """Batch64 with every set's tree an octree (same bucket size per set)."""
+    import numpy as np
+    import torch
+    from paper_1910_02639_amd import btree
+    sizes = [len(s[0]) for s in sets]
+    n = int(sum(sizes))
+    host = [np.concatenate([s[c] for s in sets]) for c in range(4)]
+    dx, dy, dz, dh = (torch.from_numpy(v).to("cuda:0") for v in host)
+    out = {}
+    for label, extra in (("btree", {}), ("octree", {"octree": True})):
+        log("octree comparison Batch64", label)
+        B = btree.Batch(sizes, [dict(p, **extra) for p in prm32], precision="fp32", timing=True)
+        counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
+        offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+        c, o, nb, totals = B.find(dx, dy, dz, dh)
+        nbrs = torch.empty(int(totals.sum()), dtype=torch.int32, device="cuda:0")
+        del c, o, nb
+        B.run(dx, dy, dz, dh, counts, offsets, nbrs)
+        torch.cuda.synchronize()
+        s0 = B.stats()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            B.run(dx, dy, dz, dh, counts, offsets, nbrs)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        st = B.stats()
+        ph = phase_delta(s0, st)
+        B.close()
+        out[label] = {"build_ms": ph["build"], "search_ms": ph["pass1"] + ph["pass2"],
+                      "ms_per_step": 1e3 * el / steps,
+                      "pair_tests_per_particle": st["pair_tests"] / n, "tree": _tree_view(st)}
+    out["build_speedup_btree_vs_octree"] = out["octree"]["build_ms"] / out["btree"]["build_ms"]
+    out["search_speedup_btree_vs_octree"] = out["octree"]["search_ms"] / out["btree"]["search_ms"]
+    return out
+
+
+def bench_build_sweep(name, buckets=(16, 32, 64, 128, 256), betas=(0.3, 0.5, 0.8), reps=5):
+    """BuildTree time alone over (s, beta), and the octree at each s (the
+    bucket-size and beta sweeps of the paper's build figures)."""
+    import torch
+    from paper_1910_02639_amd import btree, workloads as W
+    x, y, z, _, _ = W.make(name)
+    dx, dy, dz = (torch.from_numpy(v).to("cuda:0") for v in (x, y, z))
+    table, depth = {}, {}
+    for s_ in buckets:
+        for key, kw in [("%d/%g" % (s_, b), {"beta": b}) for b in betas] + \
+                       [("%d/octree" % s_, {"octree": True})]:
+            t = btree.BTree(dx, dy, dz, bucket_size=s_, timing=True, **kw)
+            for _ in range(reps):
+                t.rebuild(dx, dy, dz)
+            torch.cuda.synchronize()
+            st = t.stats()
+            t.close()
+            table[key] = st["phase_ms"]["build"] / st["phase_calls"]["build"]
+            depth[key] = st["depth"]
+    log("build sweep", name, "done")
+    return {"workload": name, "build_ms": table, "depth": depth}
+
+
+def bench_density_and_adapt(name, steps=5):
+    """The fused density (no lists) against the lists (both passes), and the
+    h adaptation from 0.7 h to the workload's target count."""
+    import torch
+    from paper_1910_02639_amd import btree, workloads as W
+    x, y, z, h, s_ = W.make(name)
+    n = len(x)
+    dx, dy, dz, dh = (torch.from_numpy(v).to("cuda:0") for v in (x, y, z, h))
+    t = btree.BTree(dx, dy, dz, bucket_size=s_)
+    counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
+    rho = torch.empty(n, dtype=torch.float64, device="cuda:0")
+    _, _, total = t.count(dh, counts, offsets)
+    nbrs = torch.empty(total, dtype=torch.int32, device="cuda:0")
+    t.density(dh, rho=rho, counts=counts)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.density(dh, rho=rho, counts=counts)
+    torch.cuda.synchronize()
+    dens_ms = 1e3 * (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.count(dh, counts, offsets)
+        t.fill(dh, counts, offsets, nbrs)
+    torch.cuda.synchronize()
+    lists_ms = 1e3 * (time.perf_counter() - t0) / steps
+    del nbrs
+    target = 64.0 if name == "U10k" else 100.0
+    h0 = dh * 0.7
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    c, rounds = t.adapt_h(h0, target, 3.0, 60)
+    torch.cuda.synchronize()
+    adapt_ms = 1e3 * (time.perf_counter() - t0)
+    within = float(((c.to(torch.float64) - target).abs() <= 3.0).double().mean())
+    t.close()
+    log("density and h adaptation", name, "done")
+    return {"workload": name, "n": n, "density_ms": dens_ms, "lists_ms": lists_ms,
+            "density_vs_lists_speedup": lists_ms / dens_ms,
+            "adapt_h": {"from": "0.7 h", "target": target, "tol": 3.0, "rounds": rounds,
+                        "ms": adapt_ms, "ms_per_round": adapt_ms / max(rounds + 1, 1),
+                        "fraction_within_tol": within}}
 
 
 def cpu_baseline_sets(sets, budget_s):
@@ -327,6 +484,10 @@ def cpu_baseline_sets(sets, budget_s):
                       "(%.1f s)" % (len(done), len(sets), npart, dt)}
 
 
+def prm32_of(out):
+    return out["_prm32"]
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -347,6 +508,13 @@ def main():
                 k: p16[k] for k in ("n", "params", "value", "ms_per_step", "phases_ms",
                                     "neighbours_total", "pair_tests_per_particle",
                                     "fp64_confirmed_fraction", "exhaustive_items", "search_hbm")}
+            if not a.no_compare:
+                out["octree_vs_btree"] = {
+                    "Batch64": bench_octree_batch(sets, prm32_of(out)),
+                    "P8M": bench_octree_single("P8M", tuner),
+                    "L1M": bench_octree_single("L1M", tuner)}
+                out["build_sweep_P8M"] = bench_build_sweep("P8M")
+                out["sph_P8M"] = bench_density_and_adapt("P8M")
             for name in ("L1M", "U10k"):
                 r, _ = bench_single(name, "fp32", max(2, min(a.steps, 10)), 2, not a.no_compare,
                                     tuner)
@@ -377,6 +545,7 @@ def main():
                      "defaults_used": tuner.defaults_used}
     if tuner.tuned_now and a.tune_out:
         tuner.save(a.tune_out)
+    out.pop("_prm32", None)
     if not a.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline_sets(sets, a.cpu_seconds)
