@@ -307,6 +307,34 @@ __device__ __forceinline__ int stripe_of(int beg) {
     return (int)(((uint32_t)beg * 2654435761u) >> 26) & (kStripes - 1);
 }
 
+// Work item of workgroup b.  Workgroups are dealt to the chip's 8 XCDs in
+// turn (XCD b mod 8), each with its own L2, and work items next to each
+// other in tree order share most candidate leaves.  So the items are cut
+// into blocks of kXcdBlock, dealt to the XCDs in turn: the r-th workgroup
+// of XCD x takes item (r / K) 8K + x K + r mod K (K = kXcdBlock), so a
+// block's items meet in one L2 while every XCD still gets a share of every
+// part of the item list (their costs vary widely along it).  The grid must
+// cover the items rounded up to a multiple of 8K (xcd_grid); returns n (no
+// item) past the end.  n must not exceed the items the per-item buffers
+// hold (callers pass min(items, capacity)): the id is not bounded by the
+// grid size.
+constexpr int kXcdBlock = 16;
+
+__device__ __forceinline__ int xcd_item(unsigned b, int n) {
+    const unsigned r = b >> 3, x = b & 7u;
+    const int64_t ci = (int64_t)(r / kXcdBlock) * (8 * kXcdBlock) + (int64_t)x * kXcdBlock +
+                       (r % kXcdBlock);
+    return ci < n ? (int)ci : n;
+}
+
+// Grid for xcd_item over `items` work items: a multiple of 8 kXcdBlock.
+inline unsigned xcd_grid(int64_t items) {
+    constexpr int64_t q = 8 * kXcdBlock;
+    int64_t g = std::max<int64_t>(1, items);
+    g = (g + q - 1) / q * q;
+    return (unsigned)std::min<int64_t>(g, 0x7fffff00);
+}
+
 // The walk as a kernel of its own, one wavefront per work item, breadth
 // first: all cells of the current tree level are expanded together (lane j
 // computes the Eq. 5 ranges of frontier cell j; then the sub-cells of all
@@ -329,15 +357,19 @@ __global__ __launch_bounds__(64) void k_walk(const Chunk* __restrict__ chunks,
                                              double* __restrict__ hs,
                                              int4* __restrict__ whdr, int2* __restrict__ wl,
                                              int64_t wl_cap, unsigned long long* __restrict__ wcur,
-                                             ItemBox* __restrict__ ibox, Ctl* __restrict__ ctl) {
+                                             ItemBox* __restrict__ ibox, Ctl* __restrict__ ctl,
+                                             const int item_cap) {
     __shared__ int32_t s_front[2][kFMax];
     __shared__ int32_t s_pref[kFMax + 1];
     __shared__ int64_t s_tab[kFMax];      // child-table offset of frontier cell j
     __shared__ uint32_t s_geo[kFMax][3];  // 16-bit pairs: (b, start x), (start y, z), (size x, y)
     __shared__ int32_t s_leaf[kLMaxWalk];
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
-    const int ci = blockIdx.x;
-    if (ci >= ctl->n_chunks) return;
+    // Items past the per-item buffers (a replay with more items than it was
+    // recorded for) are left alone; the sweep reports the overflow.
+    const int nit = min(ctl->n_chunks, item_cap);
+    const int ci = xcd_item(blockIdx.x, nit);
+    if (ci >= nit) return;
     const Chunk ch = chunks[ci];
     const int lane = threadIdx.x;
     const bool qv = lane < ch.cnt;
@@ -1097,19 +1129,42 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     if constexpr (OUT == kOutDensity) {
         // The lane's hits in its block, in ascending index.
         if (!small) {
+            // Each neighbour's coordinates (and mass) are loaded one hit
+            // ahead of their use, so a load is in flight while the previous
+            // term is evaluated.
             double acc = 0.0;
             const int wbase = kMaxW - nw;
+            const double hq = 0.5 * R;
 #pragma unroll
             for (int i = 0; i < kMaxW; ++i) {
                 const int wi = i - wbase;
                 if (wi >= 0 && qv) {
                     uint32_t word = wq[i];
                     const int kb = k0 + 32 * wi;
+                    double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
+                    double mj = 1.0;
+                    if (word) {
+                        const int key = Ent<F32>::key(cand(kb + __clz(word)));
+                        o = orig[key];
+                        if (dout.mass) mj = dout.mass[key];
+                    }
                     while (word) {
-                        const int j = __clz(word);
-                        word &= ~(0x80000000u >> j);
-                        acc += sph_term(qp.x, qp.y, qp.z, 0.5 * R, Ent<F32>::key(cand(kb + j)),
-                                        orig, dout.mass);
+                        word &= ~(0x80000000u >> __clz(word));
+                        double4 on = o;
+                        double mn = mj;
+                        if (word) {
+                            const int key = Ent<F32>::key(cand(kb + __clz(word)));
+                            on = orig[key];
+                            if (dout.mass) mn = dout.mass[key];
+                        }
+                        const double dx = __dsub_rn(qp.x, o.x), dy = __dsub_rn(qp.y, o.y);
+                        const double dz = __dsub_rn(qp.z, o.z);
+                        const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                                    __dmul_rn(dz, dz));
+                        const double wv = sph_shape(d2, hq);
+                        acc += dout.mass ? __dmul_rn(mj, wv) : wv;
+                        o = on;
+                        mj = mn;
                     }
                 }
             }
@@ -1268,13 +1323,15 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                const int2* __restrict__ wl,
                                                const ItemBox* __restrict__ ibox,
                                                Stats* __restrict__ stats, const int excl,
-                                               const DensOut dout) {
+                                               const DensOut dout, const int item_cap) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
+    // More items than the per-item buffers hold (a replay recorded for fewer):
+    // the host grows them and records again.
     const int nch = ctl->n_chunks;
-    const int ci = blockIdx.x;
-    if (ci == 0 && threadIdx.x == 0 && (unsigned)nch > gridDim.x)
-        atomicOr(&ctl->overflow, kOvfChunks);
-    if (ci >= nch) return;
+    if (blockIdx.x == 0 && threadIdx.x == 0 && nch > item_cap) atomicOr(&ctl->overflow, kOvfChunks);
+    const int nit = min(nch, item_cap);
+    const int ci = xcd_item(blockIdx.x, nit);
+    if (ci >= nit) return;
     const Chunk ch = chunks[ci];
     const int C = sweep_item<F32, 1, kCMax, kLMax, false, OUT>(
         ci, ch, whdr, wl, ibox, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
@@ -1796,9 +1853,11 @@ constexpr unsigned kBruteGrid = 512;
 constexpr int64_t kWalkPerItem = 64;  // mean leaf entries per item the walk pool holds
 constexpr unsigned kSplitGrid = 1024;
 
+// item_cap: work items the per-item buffers hold (the grid covers them).
 template <bool F32, int OUT>
-void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, DensOut dout,
+void launch_sweep(Tree& t, const double* h, int32_t* counts, int item_cap, DensOut dout,
                   hipStream_t st) {
+    const unsigned grid = xcd_grid(item_cap);
     hipLaunchKernelGGL((k_sweep<F32, OUT>), dim3(grid), dim3(kWG), 0, st, t.chunks.as<Chunk>(),
                        t.pos.as<double4>(), t.orig.as<double4>(), t.nodes.as<Node>(),
                        t.ctab.as<int32_t>(), t.leaves.as<Leaf>(), t.lrange.as<int2>(),
@@ -1806,7 +1865,7 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, unsigned grid, Dens
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.split_ci.as<int32_t>(),
                        t.whdr.as<int4>(), t.wl.as<int2>(), t.ibox.as<ItemBox>(),
-                       t.stats.as<Stats>(), t.prm.exclude_self, dout);
+                       t.stats.as<Stats>(), t.prm.exclude_self, dout, item_cap);
     BT_LAUNCH();
 }
 
@@ -1898,22 +1957,23 @@ void find_begin(Tree& t, const double* h, hipStream_t st) {
 }
 
 void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st) {
-    const unsigned g = (unsigned)std::max<int64_t>(1, grid);
+    const int cap = (int)std::min<int64_t>(std::max<int64_t>(grid, 1), INT32_MAX);
+    const unsigned g = xcd_grid(cap);
     hipLaunchKernelGGL(k_walk, dim3(g), dim3(64), 0, st, t.chunks.as<Chunk>(), t.pos.as<double4>(),
                        t.nodes.as<Node>(), t.ctab.as<int32_t>(), t.leaves.as<Leaf>(),
                        t.lrange.as<int2>(), t.sets.as<SetDev>(), h, t.hs.as<double>(),
                        t.whdr.as<int4>(),
                        t.wl.as<int2>(), t.wl_cap,
                        t.stripes.as<unsigned long long>() + kStripes * kStripeStride,
-                       t.ibox.as<ItemBox>(), t.ctl.as<Ctl>());
+                       t.ibox.as<ItemBox>(), t.ctl.as<Ctl>(), cap);
     BT_LAUNCH();
 }
 
 void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStream_t st) {
-    const unsigned g = (unsigned)std::max<int64_t>(1, grid);
+    const int cap = (int)std::min<int64_t>(std::max<int64_t>(grid, 1), INT32_MAX);
     const DensOut none{nullptr, nullptr};
-    if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true, kOutRows>(t, h, counts, g, none, st);
-    else launch_sweep<false, kOutRows>(t, h, counts, g, none, st);
+    if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true, kOutRows>(t, h, counts, cap, none, st);
+    else launch_sweep<false, kOutRows>(t, h, counts, cap, none, st);
 }
 
 void find_counts_end(Tree& t, const double* h, int32_t* counts, int64_t* offsets, hipStream_t st) {
@@ -1929,7 +1989,7 @@ void find_no_rows(Tree& t, const double* h, int32_t* counts, const double* mass,
                   hipStream_t st) {
     find_reserve(t, std::max<int64_t>(t.scap, 1));
     const DensOut d{mass, rho};
-    const unsigned g = (unsigned)std::max<int64_t>(1, t.n_chunks);
+    const int g = (int)std::max<int64_t>(t.n_chunks, 1);  // items the buffers hold
     find_begin(t, h, st);
     find_walk(t, h, t.n_chunks, st);
     t.timer.start(kPhSweep, st);
