@@ -42,6 +42,12 @@
 //    FP64 predicate on the original coordinates.  Items whose spread or
 //    radius reaches 2^60 (where FP32 squares could overflow) take FP64
 //    arithmetic.
+//    The words of the main test fold the threshold into the sum: with
+//    T = fl32(R^2), E = fl(tz^2 + fl(ty^2 + fl(tx^2 - T))) (three FMAs) is
+//    within kap (|t|^2 + T) + ea of |t|^2 - T (kap = 3u (1 + 2^-20)), so a
+//    margin M (set-up in sweep_item) makes E < -M certify a neighbour and
+//    E >= M a non-neighbour; the bit is E's sign bit and a word whose
+//    smallest |E| is at most M is classified again candidate by candidate.
 #include "prim.h"
 
 #include <algorithm>
@@ -657,8 +663,10 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         if (F32) item_bounds(qv, qp, R, elo, ehi, sn, rmax);
     }
 
-    // FP32 filter set-up (derivation at the top of the file).
-    float ax = 0.f, ay = 0.f, az = 0.f, tlo = -1.f, thi = -1.f;
+    // FP32 filter set-up (derivation at the top of the file).  tlo, thi:
+    // the thresholds on D (the lane-per-candidate test of small units);
+    // nT, tM: the threshold and margin of the three-FMA test of the words.
+    float ax = 0.f, ay = 0.f, az = 0.f, tlo = -1.f, thi = -1.f, nT = 1.f, tM = -1.f;
     double cx = 0.0, cy = 0.0, cz = 0.0;
     bool unsafe = false;
     if (F32) {
@@ -680,6 +688,28 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 (1.0 + g3) * (1.0 + u) * (1.0 + u) * B * B * (1.0 + 0x1p-40) + 8.0 * 0x1p-126;
             tlo = tl > 0.0 ? f32_down(tl) : 0.0f;
             thi = f32_up(th);
+            // Three-FMA test: E = fl(tz^2 + fl(ty^2 + fl(tx^2 - T))), T = fl32(R^2).
+            // Each FMA rounds once, so |E - (|t|^2 - T)| <= kap (|t|^2 + T) + ea
+            // with kap = 3u (1 + 2^-20) and ea an absolute slack for results
+            // flushed to zero.  The filter's bounds on |t|^2 are Qlo (below it
+            // the pair is a neighbour) and Qhi (at or above it, not one): D's
+            // thresholds above are Qlo and Qhi widened by gamma_3.  Hence
+            //   E < -M => |t|^2 < (T (1 + kap) - M + ea) / (1 - kap) <= Qlo,
+            //   E >= M => |t|^2 >= (T (1 - kap) + M - ea) / (1 + kap) >= Qhi,
+            // for M = max(T (1 + kap) + ea - Qlo (1 - kap),
+            //             Qhi (1 + kap) - T (1 - kap) + ea),
+            // computed in FP64 with a slack of 2^-48 (T + Qhi) for its own
+            // roundings (the difference cancels) and rounded up to FP32.
+            // A pair with |E| <= M is decided by the FP64 predicate.
+            const double Td = (double)(float)(R * R);
+            const double kap = 3.0 * u * (1.0 + 0x1p-20);
+            const double ea = 16.0 * 0x1p-126;
+            const double Qlo = (1.0 - u) * (1.0 - u) * A * A * (1.0 - 0x1p-40);
+            const double Qhi = (1.0 + u) * (1.0 + u) * B * B * (1.0 + 0x1p-40);
+            const double m1 = Td * (1.0 + kap) + ea - Qlo * (1.0 - kap);
+            const double m2 = Qhi * (1.0 + kap) - Td * (1.0 - kap) + ea;
+            nT = -(float)Td;
+            tM = f32_up((m1 > m2 ? m1 : m2) + (Td + Qhi) * 0x1p-48);
             ax = (float)(qp.x - cx);
             ay = (float)(qp.y - cy);
             az = (float)(qp.z - cz);
@@ -984,7 +1014,8 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
 #pragma unroll
     for (int i = 0; i < kMaxW; ++i) wq[i] = 0u;
     int hits = 0;
-    unsigned long long conf = 0;
+    unsigned long long conf = 0;   // FP64 confirmations, the same in every lane
+    unsigned long long lconf = 0;  // ... counted per lane (words of the three-FMA test)
     // (Density form: per-query sums of the wavefront's part, in LDS.)
     double* s_dens = nullptr;
     if constexpr (OUT == kOutDensity) {
@@ -1017,7 +1048,15 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         const int m = min(32, k1 - kw);
         uint32_t word = 0;
         if constexpr (F32) {
-            uint32_t lword = 0;
+            // Bit = sign of E (the three-FMA test, set-up above), entering at
+            // the bottom of the word; mn = the word's smallest |E|.
+            float mn = INFINITY;
+            auto test = [&](const float4& e) {
+                const float tx = ax - e.x, ty = ay - e.y, tz = az - e.z;
+                const float E = fmaf(tz, tz, fmaf(ty, ty, fmaf(tx, tx, nT)));
+                word = __builtin_amdgcn_alignbit(word, __float_as_uint(E), 31);
+                mn = fminf(mn, fabsf(E));
+            };
             if (m == 32) {
                 for (int g = 0; g < 32; g += 8) {
                     float4 e[8];
@@ -1031,33 +1070,36 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                         for (int j = 0; j < 8; ++j)
                             e[j] = s_cand[(pw[j >> 1] >> (16 * (j & 1))) & 0xffffu];
                     }
-                    float D[8];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const float tx = ax - e[j].x, ty = ay - e[j].y, tz = az - e[j].z;
-                        D[j] = fmaf(tz, tz, fmaf(ty, ty, tx * tx));
-                    }
-                    push4_f32(word, lword, D[0], D[1], D[2], D[3], tlo, thi);
-                    push4_f32(word, lword, D[4], D[5], D[6], D[7], tlo, thi);
+                    for (int j = 0; j < 8; ++j) test(e[j]);
                 }
             } else {
-                for (int j = 0; j < m; ++j) {
-                    const float4 e = cand(kw + j);
-                    const float tx = ax - e.x, ty = ay - e.y, tz = az - e.z;
-                    push1_f32(word, lword, fmaf(tz, tz, fmaf(ty, ty, tx * tx)), tlo, thi);
-                }
+                for (int j = 0; j < m; ++j) test(cand(kw + j));
                 word <<= (32 - m);
-                lword <<= (32 - m);
             }
-            uint32_t band = lword & ~word;
-            const uint64_t bm = __ballot(band != 0u);
-            if (bm) {
-                conf += __popcll(bm);
-                while (band) {
-                    const int j = __clz(band);
-                    band &= ~(0x80000000u >> j);
-                    const double4 o = orig[__float_as_int(cand(kw + j).w)];
-                    if (p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z)) word |= 0x80000000u >> j;
+            // A word holding a pair with |E| <= M: every candidate of it is
+            // classified again (E < -M: neighbour, E >= M: not; otherwise
+            // the FP64 predicate decides).
+            if (__ballot(mn <= tM)) {
+                if (mn <= tM) {
+                    uint32_t nwd = 0;
+                    for (int j = 0; j < m; ++j) {
+                        const float4 e = cand(kw + j);
+                        const float tx = ax - e.x, ty = ay - e.y, tz = az - e.z;
+                        const float E = fmaf(tz, tz, fmaf(ty, ty, fmaf(tx, tx, nT)));
+                        uint32_t bit;
+                        if (E < -tM) {
+                            bit = 1u;
+                        } else if (E >= tM) {
+                            bit = 0u;
+                        } else {
+                            ++lconf;
+                            const double4 o = orig[__float_as_int(e.w)];
+                            bit = p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z) ? 1u : 0u;
+                        }
+                        nwd = (nwd << 1) | bit;
+                    }
+                    word = m == 32 ? nwd : nwd << (32 - m);
                 }
             }
         } else {
@@ -1124,6 +1166,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 }
         }
     }
+    if (__ballot(lconf != 0ull)) conf += wave_sum(lconf);
     if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
     if (!small) s_cnt[w][lane] = hits;
     if constexpr (OUT == kOutDensity) {
