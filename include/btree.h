@@ -98,9 +98,10 @@ typedef struct {
     int64_t candidates;     /* culled candidates staged, summed over items    */
     /* with params.timing = 1, device time of each phase summed over the
        calls since btree_build (btree_rebuild keeps counting):
-       [0] build, [1] search sweep kernel (walk, stage, test, rows to the
-       handle's scratch), [2] placement kernel (rows into the caller's CSR;
-       in the batched form the whole placement segment, exhaustive rows
+       [0] build, [1] search sweep kernel (walk, stage, test, rows or test
+       words to the handle's scratch), [2] placement kernels (rows into the
+       caller's CSR, expanded from the words or copied from the scratch; in
+       the batched form the whole placement segment, exhaustive rows
        included), [3] whole pass 1, [4] whole pass 2;
        phase_calls counts the calls.                                      */
     double  phase_ms[5];
@@ -111,6 +112,11 @@ typedef struct {
     int64_t brute_units;    /* units (1 to 64 queries of one set) that took
                                the exhaustive path; brute_chunks counts their
                                queries                                          */
+    int64_t word_items;     /* work items of the main sweep whose rows pass 2
+                               expanded from their test words (the items
+                               whose words take less room than their rows)  */
+    int64_t word_items_wide; /* of those, items with more than 8192 row
+                               entries (expanded in windows)                  */
 } btree_stats_t;
 
 typedef struct btree_tree* btree_handle;

@@ -53,7 +53,8 @@ class Stats(ctypes.Structure):
                 ("pair_tests", ctypes.c_int64), ("fp64_confirms", ctypes.c_int64),
                 ("brute_chunks", ctypes.c_int64), ("candidates", ctypes.c_int64),
                 ("phase_ms", ctypes.c_double * 5), ("phase_calls", ctypes.c_int64 * 5),
-                ("split_items", ctypes.c_int64), ("brute_units", ctypes.c_int64)]
+                ("split_items", ctypes.c_int64), ("brute_units", ctypes.c_int64),
+                ("word_items", ctypes.c_int64), ("word_items_wide", ctypes.c_int64)]
 
 PHASES = ["build", "sweep_kernel", "place_kernel", "pass1", "pass2"]
 

@@ -347,11 +347,13 @@ btree_status btree_batch_stats(btree_batch_handle H, btree_stats_t* out) {
     out->n_chunks = t.n_chunks;
     for (int k = 0; k < 65; ++k) out->b_hist[k] = (int64_t)t.host_stats.b_hist[k];
     out->total = t.last_total;
-    out->pair_tests = (int64_t)t.host_stats.pair_tests;
-    out->fp64_confirms = (int64_t)t.host_stats.confirms;
-    out->brute_chunks = (int64_t)t.host_stats.brute;
-    out->candidates = (int64_t)t.host_stats.candidates;
-    out->split_items = (int64_t)t.host_stats.split;
+    out->pair_tests = (int64_t)ctr_total(t.host_stats, kCtrPairs);
+    out->fp64_confirms = (int64_t)ctr_total(t.host_stats, kCtrConfirms);
+    out->brute_chunks = (int64_t)ctr_total(t.host_stats, kCtrBrute);
+    out->candidates = (int64_t)ctr_total(t.host_stats, kCtrCands);
+    out->split_items = (int64_t)ctr_total(t.host_stats, kCtrSplit);
+    out->word_items = (int64_t)ctr_total(t.host_stats, kCtrWords);
+    out->word_items_wide = (int64_t)ctr_total(t.host_stats, kCtrWide);
     out->brute_units = (int64_t)t.host_ctl.nbunits;
     for (int k = 0; k < kPhases; ++k) {
         out->phase_ms[k] = t.timer.sum_ms[k];

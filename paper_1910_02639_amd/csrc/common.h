@@ -168,15 +168,6 @@ struct Chunk {
 
 constexpr int kGroup = 64;  // queries per work item (one per lane)
 
-struct Stats {  // device-side counters
-    unsigned long long rounds;
-    unsigned long long pair_tests;
-    unsigned long long confirms;
-    unsigned long long brute;
-    unsigned long long candidates;
-    unsigned long long split;
-    unsigned long long b_hist[65];
-};
 
 // One independent particle set (a batch holds several, a tree one).
 struct SetDev {
@@ -250,6 +241,25 @@ struct Ctl {
 constexpr int kStripes = 64;
 constexpr int64_t kDenseTaskCap = 16384;  // exhaustive tasks whose counts the fill pass reuses
 constexpr int kStripeStride = 16;  // uint64 per cursor slot
+
+// Device-side counters.  The search's counters are added to once per work
+// item, so they are striped like the cursors (work item -> stripe_of its
+// first particle): one line shared by every workgroup serialises their
+// atomics, which then bound the whole sweep.  The host sums the stripes.
+enum { kCtrPairs = 0, kCtrCands, kCtrConfirms, kCtrBrute, kCtrSplit, kCtrWords, kCtrWide,
+       kCtrCount };
+struct Stats {
+    unsigned long long rounds;
+    unsigned long long b_hist[65];
+    alignas(128) unsigned long long ctr[kStripes][kStripeStride];
+};
+static_assert(kCtrCount <= kStripeStride, "counters must fit a stripe's line");
+
+inline unsigned long long ctr_total(const Stats& s, int k) {
+    unsigned long long v = 0;
+    for (int i = 0; i < kStripes; ++i) v += s.ctr[i][k];
+    return v;
+}
 
 constexpr int kPersistBlocks = 2048;  // grid of the persistent per-cell / per-item kernels
 
@@ -340,6 +350,7 @@ struct Tree {
     DBuf hs;       // double per particle: h in tree order (filled by each search)
     DBuf whdr;     // int4 per work item: walk result header
     DBuf ibox;     // per work item: box E and the FP32 filter's item-wide bounds (64 bytes)
+    DBuf irec;     // per work item: where pass 1 left its test words and candidates
     DBuf wl;       // int2 pool: candidate leaves (first particle, count) of every item
     DBuf aux_counts;  // int32 per particle, when a caller passes no counts buffer
     DBuf adapt_br;    // double2 per particle: bracket (lo, hi) of the h adaptation
@@ -349,6 +360,7 @@ struct Tree {
     int64_t n_internal = 0, n_leaves = 0, n_chunks = 0, ctab_len = 0;
     int64_t scap = 0;  // scratch capacity, entries
     int64_t chunk_cap = 0;  // work items a captured search launches for
+    int64_t sweep_cap = 0;  // item bound of the last rows pass 1 (its pass 2 uses the same)
     int64_t wl_cap = 0;     // entries of the walk-list pool
     int64_t wl_need = 0;    // pool size the last walk needed, when the pool was too small
     unsigned long long host_stripes[2 * kStripes * kStripeStride] = {};

@@ -62,6 +62,10 @@ constexpr int kWaves = kWG / 64;
 constexpr int kLMax = 512;   // candidate leaves per item
 constexpr int kSMax = 256;   // walk stack entries
 constexpr int kCMax = 1536;  // staged candidates per item (both forms)
+// An item of the main sweep leaves its test words for k_expand when
+// their size times kBitsNum / kBitsDen is below the size of its rows.
+constexpr int kBitsNum = 1, kBitsDen = 1;
+constexpr int kRowBuf = 8192;  // entries of k_expand's shared-memory row image
 constexpr int kBuckets = 256;       // original-index buckets of the staged list
 constexpr int kBucketSortMax = 48;  // a fuller bucket sorts the whole item instead
 
@@ -287,6 +291,17 @@ __device__ __forceinline__ void item_box(bool qv, const double4& qp, double R, d
 struct ItemBox {
     double lo[3], hi[3];
     double sn, rmax;
+};
+
+// Where pass 1 left a main-sweep work item's result for pass 2 (off < 0:
+// nowhere, the item's rows went through the split path or did not fit):
+// at scratch[off], the test words, word g of query q at g * qs + q (qs: the
+// item's queries), then its C candidates' set-local indices in ascending
+// order.  Bit 31 - j of word g is the pair (query, candidate 32 g + j).
+struct ItemRows {
+    int64_t off;
+    int32_t C;
+    int32_t qs;
 };
 
 __device__ __forceinline__ void item_bounds(bool qv, const double4& qp, double R,
@@ -606,8 +621,14 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                                            int32_t* __restrict__ scratch, int64_t scap,
                                            unsigned long long* __restrict__ scur, int stripe,
                                            Ctl* __restrict__ ctl, Stats* __restrict__ stats,
-                                           const int excl, const DensOut dout) {
+                                           const int excl, const DensOut dout,
+                                           ItemRows* __restrict__ irec) {
     using E = typename Ent<F32>::T;
+    // The main sweep's rows form leaves the test words and the ordered
+    // candidates for pass 2 (k_expand), which writes the rows straight into
+    // the caller's CSR once the offsets are known; the split levels write
+    // rows to the scratch (k_place copies them).
+    constexpr bool kBits = OUT == kOutRows && WALK == 1 && !SMALL;
     constexpr int kMaxW = ((CMAX / kWaves) + 31) / 32;  // bit words per lane and wavefront
     __shared__ E s_cand[CMAX];
     __shared__ int32_t s_cnt[kWaves][64];
@@ -624,7 +645,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     __shared__ int32_t s_bcur[kBuckets];  // placement cursors, then bucket ends
     __shared__ int32_t s_qoff[64];
     __shared__ int64_t s_scan[kWaves + 1];
-    __shared__ int s_nleaf, s_ovf, s_kmin, s_kmax, s_C, s_big, s_total;
+    __shared__ int s_nleaf, s_ovf, s_kmin, s_kmax, s_C, s_big, s_total, s_bits, s_rows_total;
     __shared__ unsigned long long s_base;
 
     // The item's set: its root, and the base that makes indices set-local.
@@ -1167,7 +1188,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         }
     }
     if (__ballot(lconf != 0ull)) conf += wave_sum(lconf);
-    if (lane == 0 && conf) atomicAdd(&stats->confirms, conf);
+    if (lane == 0 && conf) atomicAdd(&stats->ctr[stripe][kCtrConfirms], conf);
     if (!small) s_cnt[w][lane] = hits;
     if constexpr (OUT == kOutDensity) {
         // The lane's hits in its block, in ascending index.
@@ -1230,14 +1251,17 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
             }
             if (lane == 0) {
                 unsigned long long tests = (unsigned long long)C * (unsigned long long)ch.cnt;
-                atomicAdd(&stats->pair_tests, tests);
-                atomicAdd(&stats->candidates, (unsigned long long)C);
+                atomicAdd(&stats->ctr[stripe][kCtrPairs], tests);
+                atomicAdd(&stats->ctr[stripe][kCtrCands], (unsigned long long)C);
             }
         }
         return 0;
     }
 
-    // Row lengths, then one scratch allocation for the item.
+    // Row lengths, then one scratch allocation for the item: its rows, or
+    // (main sweep) its test words and candidates when they take less room
+    // than the rows (k_expand's cost goes with the items, k_place's with
+    // the rows, so items of few queries or few hits keep their rows).
     if (w == 0) {
         int c = 0;
 #pragma unroll
@@ -1245,12 +1269,21 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         if (!qv) c = 0;
         const int inc = wave_incl_scan(c);
         s_qoff[lane] = inc - c;
-        const int total = __builtin_amdgcn_readlane(inc, 63);
+        const int rows_total = __builtin_amdgcn_readlane(inc, 63);
+        int total = rows_total;
+        bool use_bits = false;
+        if constexpr (kBits) {
+            const int btotal = ((C + 31) >> 5) * ch.cnt + C;
+            use_bits = kBitsNum * btotal < kBitsDen * total;
+            if (use_bits) total = btotal;
+        }
         if (lane == 0) {
+            s_bits = use_bits ? 1 : 0;
+            s_rows_total = rows_total;
             s_total = total;
             s_base = atomicAdd(&scur[stripe * kStripeStride], (unsigned long long)total);
-            atomicAdd(&stats->pair_tests, (unsigned long long)C * (unsigned long long)ch.cnt);
-            atomicAdd(&stats->candidates, (unsigned long long)C);
+            atomicAdd(&stats->ctr[stripe][kCtrPairs], (unsigned long long)C * (unsigned long long)ch.cnt);
+            atomicAdd(&stats->ctr[stripe][kCtrCands], (unsigned long long)C);
         }
         if (qv) counts[qidx] = c;
     }
@@ -1262,9 +1295,31 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         // Scratch too small this time: counts are right; the rows are redone
         // once the scratch has grown to the need the cursors now hold.
         if (t == 0) atomicOr(&ctl->overflow, kOvfScratch);
+        if (kBits && t == 0) irec[ci] = ItemRows{-1, 0, 0};
         if (w == 0 && qv) soff[qidx] = -2;
         return 0;
     }
+    if (kBits && s_bits) {
+        // Words: wavefront w's g-th word of query q at (w B / 32 + g) qs + q,
+        // stored by the item's lanes together; then the candidates.
+        const int qs = ch.cnt;
+        const int g0 = k0 >> 5;
+#pragma unroll
+        for (int i = 0; i < kMaxW; ++i) {
+            const int wi = i - (kMaxW - nw);
+            if (wi >= 0 && qv) scratch[base + (int64_t)(g0 + wi) * qs + lane] = (int32_t)wq[i];
+        }
+        const int64_t kbase = base + (int64_t)((C + 31) >> 5) * qs;
+        for (int k = t; k < C; k += kWG) scratch[kbase + k] = Ent<F32>::key(cand(k)) - sbeg;
+        if (w == 0 && qv) soff[qidx] = -3;  // k_place leaves the row to k_expand
+        if (t == 0) {
+            irec[ci] = ItemRows{base, C, qs};
+            atomicAdd(&stats->ctr[stripe][kCtrWords], 1ull);
+            if (s_rows_total > kRowBuf) atomicAdd(&stats->ctr[stripe][kCtrWide], 1ull);
+        }
+        return 0;
+    }
+    if (kBits && t == 0) irec[ci] = ItemRows{-1, 0, 0};  // rows through k_place
     if (w == 0 && qv) soff[qidx] = base + s_qoff[lane];
     if (small) {
         unsigned long long unused = 0;
@@ -1366,7 +1421,8 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
                                                const int2* __restrict__ wl,
                                                const ItemBox* __restrict__ ibox,
                                                Stats* __restrict__ stats, const int excl,
-                                               const DensOut dout, const int item_cap) {
+                                               const DensOut dout, ItemRows* __restrict__ irec,
+                                               const int item_cap) {
     if (ctl->data_bad || (ctl->overflow & kOvfTree)) return;
     // More items than the per-item buffers hold (a replay recorded for fewer):
     // the host grows them and records again.
@@ -1378,12 +1434,13 @@ __global__ __launch_bounds__(kWG) void k_sweep(const Chunk* __restrict__ chunks,
     const Chunk ch = chunks[ci];
     const int C = sweep_item<F32, 1, kCMax, kLMax, false, OUT>(
         ci, ch, whdr, wl, ibox, pos, orig, nodes, ctab, leaves, lrange, sets, h, counts, soff,
-        scratch, scap, scur, stripe_of(ch.beg), ctl, stats, excl, dout);
+        scratch, scap, scur, stripe_of(ch.beg), ctl, stats, excl, dout, irec);
     if (C && threadIdx.x == 0) {
+        if (OUT == kOutRows) irec[ci] = ItemRows{-1, 0, 0};
         const uint32_t k = atomicAdd(&ctl->nsplit, 1u);
         split[k] = Chunk{ch.beg, ch.cnt, ch.set, C};
         split_ci[k] = ci;
-        atomicAdd(&stats->split, 1ull);
+        atomicAdd(&stats->ctr[stripe_of(ch.beg)][kCtrSplit], 1ull);
     }
 }
 
@@ -1401,7 +1458,7 @@ __device__ __forceinline__ void to_brute(const Chunk q, const double4* __restric
     if (threadIdx.x == 0) {
         brute[atomicAdd(&ctl->nbrute, 1u)] = Chunk{q.beg, q.cnt, q.set, 0};
         atomicAdd(&bcnt[q.set], q.cnt);
-        atomicAdd(&stats->brute, (unsigned long long)q.cnt);
+        atomicAdd(&stats->ctr[stripe_of(q.beg)][kCtrBrute], (unsigned long long)q.cnt);
     }
 }
 
@@ -1475,7 +1532,7 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
         const int C = sweep_item<F32, 2, kCMaxSplit<F32>, kLMaxSplit, (LEVEL >= 2), OUT>(
             ci, unit, whdr, wl, LEVEL == 1 ? ibox : nullptr, pos, orig, nodes, ctab, leaves, lrange,
             sets, h, counts, soff, scratch, scap, scur, stripe_of(unit.beg), ctl, stats, excl,
-            dout);
+            dout, nullptr);
         if (!C) continue;
         __syncthreads();
         if (LEVEL == 3 || (nset <= kDenseSet && C != kNoCount && 4 * (int64_t)C > nset)) {
@@ -1553,6 +1610,143 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
             for (int k = lane + 128; k < c1; k += 64) nbrs[d1 + k] = scratch[s1 + k];
             for (int k = lane + 128; k < c2; k += 64) nbrs[d2 + k] = scratch[s2 + k];
             for (int k = lane + 128; k < c3; k += 64) nbrs[d3 + k] = scratch[s3 + k];
+        }
+    }
+}
+
+// Pass 2 of the main sweep's work items: the test words and ordered
+// candidates that pass 1 left in the scratch (ItemRows) are expanded into
+// the caller's CSR rows, which saves the scratch round trip of the rows
+// (they are several times larger than the words).  The expansion is the
+// sweep's: lane q of wavefront w takes query q's words over w's quarter of
+// the candidates and puts its hits after those of the lower wavefronts
+// (ascending original index) into a shared-memory image of the item's rows,
+// as 16-bit candidate numbers; then each wavefront copies whole rows out
+// with consecutive lanes on consecutive entries, so that every line leaves
+// the L2 whole (rows stored lane by lane reach HBM as partial lines, at a
+// fraction of the bandwidth).  Rows longer than the image go through it in
+// windows of kRowBuf entries.  A row is written only when its words hold
+// exactly the count pass 1 recorded, so every store stays inside the row's
+// own range of the CSR.
+__global__ __launch_bounds__(kWG) void k_expand(const Chunk* __restrict__ chunks,
+                                                const ItemRows* __restrict__ irec,
+                                                const double4* __restrict__ pos,
+                                                const int32_t* __restrict__ counts,
+                                                const int64_t* __restrict__ offsets,
+                                                const int32_t* __restrict__ scratch, int64_t scap,
+                                                int32_t* __restrict__ nbrs, int64_t n,
+                                                int64_t capacity, const Ctl* __restrict__ ctl,
+                                                const int item_cap, const unsigned blocks) {
+    constexpr int kMaxW = ((kCMax / kWaves) + 31) / 32;
+    static_assert(kCMax <= 65536, "candidate numbers are 16-bit");
+    __shared__ int32_t s_key[kCMax];
+    __shared__ uint16_t s_rows[kRowBuf];
+    __shared__ int32_t s_cnt[kWaves][64];
+    __shared__ int32_t s_cq[64];
+    __shared__ int64_t s_dst[64];
+    // Nothing is written after a failed pass 1 or when the rows do not fit
+    // (k_place raises that flag).
+    if (ctl->data_bad || (ctl->overflow & (kOvfTree | kOvfChunks | kOvfScratch))) return;
+    if (offsets[n] > capacity) return;
+    const int nit = min(ctl->n_chunks, item_cap);
+    const int t = threadIdx.x, lane = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    // The stride keeps each workgroup on its XCD in the sweep's item order.
+    for (unsigned b = blockIdx.x; b < blocks; b += gridDim.x) {
+        const int ci = xcd_item(b, nit);
+        if (ci >= nit) continue;
+        const ItemRows r = irec[ci];
+        const Chunk ch = chunks[ci];
+        const int C = r.C, qs = r.qs;
+        const int64_t nwt = (C + 31) >> 5;
+        if (r.off < 0 || C <= 0 || C > kCMax || qs != ch.cnt || r.off + nwt * qs + C > scap)
+            continue;
+        const int32_t* const words = scratch + r.off;
+        const int32_t* const keys = words + nwt * qs;
+        const bool qv = lane < qs;
+        // Wavefront 0 fetches the queries' counts and destinations while
+        // every wavefront fetches its words.
+        int cq = -1;
+        int64_t dq = 0;
+        if (w == 0 && qv) {
+            const int qidx = (int)pos[ch.beg + lane].w;
+            cq = counts[qidx];
+            dq = offsets[qidx];
+        }
+        __syncthreads();  // the previous item is done with the shared memory
+        for (int k = t; k < C; k += kWG) s_key[k] = keys[k];
+        // This wavefront's block of candidates, as in the sweep.
+        const int B = ((C + kWaves * 32 - 1) / (kWaves * 32)) * 32;
+        const int k0 = w * B;
+        const int k1 = min(k0 + B, C);
+        const int nw = (k1 > k0) ? (k1 - k0 + 31) >> 5 : 0;
+        uint32_t wq[kMaxW];
+        int hits = 0;
+#pragma unroll
+        for (int i = 0; i < kMaxW; ++i) {
+            wq[i] = (i < nw && qv) ? (uint32_t)words[((k0 >> 5) + i) * (int64_t)qs + lane] : 0u;
+            hits += __popc(wq[i]);
+        }
+        s_cnt[w][lane] = hits;
+        if (w == 0) {
+            s_cq[lane] = cq;
+            s_dst[lane] = dq;
+        }
+        __syncthreads();
+        // Every wavefront: row lengths (0 for a row that does not match its
+        // count) and their offsets in the item's row image.
+        int tot = 0, before = 0;
+#pragma unroll
+        for (int k = 0; k < kWaves; ++k) {
+            const int c = s_cnt[k][lane];
+            tot += c;
+            if (k < w) before += c;
+        }
+        const int len = (qv && tot == s_cq[lane]) ? tot : 0;
+        const int inc = wave_incl_scan(len);
+        const int qoff = inc - len;
+        const int total = __builtin_amdgcn_readlane(inc, 63);
+        const int lo = qoff + before;  // this lane's first entry in the image
+        for (int r0 = 0; r0 < total; r0 += kRowBuf) {
+            const int r1 = r0 + kRowBuf;
+            if (len > 0 && lo < r1 && lo + hits > r0) {
+                // The common case, the whole image at once, needs no bounds
+                // per entry.
+                const bool whole = total <= kRowBuf;
+                int at = lo - r0;
+#pragma unroll
+                for (int i = 0; i < kMaxW; ++i) {
+                    if (i < nw) {
+                        uint32_t word = wq[i];
+                        const int kb = k0 + 32 * i;
+                        if (whole) {
+                            while (word) {
+                                const int j = __clz(word);
+                                word &= ~(0x80000000u >> j);
+                                s_rows[at++] = (uint16_t)(kb + j);
+                            }
+                        } else {
+                            while (word) {
+                                const int j = __clz(word);
+                                word &= ~(0x80000000u >> j);
+                                if (at >= 0 && at < kRowBuf) s_rows[at] = (uint16_t)(kb + j);
+                                ++at;
+                            }
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+            // Whole rows (their parts in this window) out, one wavefront per row.
+            for (int q = w; q < qs; q += kWaves) {
+                const int lq = __builtin_amdgcn_readlane(len, q);
+                if (lq <= 0) continue;
+                const int sq = __builtin_amdgcn_readlane(qoff, q);
+                const int a = max(sq, r0), e = min(sq + lq, r1);
+                int32_t* const dst = nbrs + s_dst[q];
+                for (int j = a + lane; j < e; j += 64) dst[j - sq] = s_key[s_rows[j - r0]];
+            }
+            if (r1 < total) __syncthreads();  // the image is refilled
         }
     }
 }
@@ -1837,12 +2031,9 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
         ctl->nadapt = 0;
         ctl->data_bad &= 1;  // keep a bad coordinate seen by the build
         ctl->overflow &= ~(kOvfScratch | kOvfCapacity | kOvfChunks | kOvfWalk);
-        stats->pair_tests = 0;
-        stats->confirms = 0;
-        stats->brute = 0;
-        stats->candidates = 0;
-        stats->split = 0;
     }
+    if (threadIdx.x < kStripes)
+        for (int k = 0; k < kCtrCount; ++k) stats->ctr[threadIdx.x][k] = 0;
 }
 
 // Brackets of the h adaptation: lo = 0 and hi = +inf (none known yet).
@@ -1881,8 +2072,16 @@ __global__ void k_adapt_h(const int32_t* __restrict__ counts, double* __restrict
         br[i] = b;
         ++mine;
     }
+    // One atomic per workgroup (the grid strides over the particles).
+    __shared__ unsigned s_mine[kWG / 64];
     mine = wave_sum(mine);
-    if (lane_id() == 0 && mine) atomicAdd(&ctl->nadapt, mine);
+    if (lane_id() == 0) s_mine[threadIdx.x >> 6] = mine;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned tot = 0;
+        for (int k = 0; k < kWG / 64; ++k) tot += s_mine[k];
+        if (tot) atomicAdd(&ctl->nadapt, tot);
+    }
 }
 
 // Lists per set: totals[k] = offsets[end of set k] - offsets[start of set k].
@@ -1893,6 +2092,7 @@ __global__ void k_set_totals(const int64_t* __restrict__ offsets, const SetDev* 
 }
 
 constexpr unsigned kBruteGrid = 512;
+constexpr unsigned kExpandGrid = 1u << 30;  // k_expand: one workgroup per item
 constexpr int64_t kWalkPerItem = 64;  // mean leaf entries per item the walk pool holds
 constexpr unsigned kSplitGrid = 1024;
 
@@ -1908,7 +2108,8 @@ void launch_sweep(Tree& t, const double* h, int32_t* counts, int item_cap, DensO
                        t.scratch.as<int32_t>(), t.scap, t.stripes.as<unsigned long long>(),
                        t.ctl.as<Ctl>(), t.split.as<Chunk>(), t.split_ci.as<int32_t>(),
                        t.whdr.as<int4>(), t.wl.as<int2>(), t.ibox.as<ItemBox>(),
-                       t.stats.as<Stats>(), t.prm.exclude_self, dout, item_cap);
+                       t.stats.as<Stats>(), t.prm.exclude_self, dout, t.irec.as<ItemRows>(),
+                       item_cap);
     BT_LAUNCH();
 }
 
@@ -1977,6 +2178,7 @@ void find_reserve(Tree& t, int64_t entries) {
     const int64_t items = std::max<int64_t>(std::max(t.n_chunks, t.chunk_cap), 1);
     t.whdr.reserve(sizeof(int4) * items);
     t.ibox.reserve(sizeof(ItemBox) * items);
+    t.irec.reserve(sizeof(ItemRows) * items);
     const int64_t wl_want = std::max(kWalkPerItem * items, t.wl_need);
     if (t.wl_cap < wl_want) {
         t.wl.release();
@@ -2014,6 +2216,7 @@ void find_walk(Tree& t, const double* h, int64_t grid, hipStream_t st) {
 
 void find_sweep(Tree& t, const double* h, int32_t* counts, int64_t grid, hipStream_t st) {
     const int cap = (int)std::min<int64_t>(std::max<int64_t>(grid, 1), INT32_MAX);
+    t.sweep_cap = cap;
     const DensOut none{nullptr, nullptr};
     if (t.prm.precision == BTREE_FP32_FILTER) launch_sweep<true, kOutRows>(t, h, counts, cap, none, st);
     else launch_sweep<false, kOutRows>(t, h, counts, cap, none, st);
@@ -2078,6 +2281,15 @@ void find_fill(Tree& t, const int32_t* counts, const int64_t* offsets, int32_t* 
         fail(BTREE_EDEVICE, "find_fill: counts or offsets missing");
     launch_dense<kFill>(t, nullptr, offsets, capacity, nbrs, DensOut{nullptr, nullptr}, st);
     if (time_place) t.timer.start(kPhPlace, st);
+    if (t.n > 0 && t.sweep_cap > 0) {
+        const int cap = (int)t.sweep_cap;
+        const unsigned blocks = xcd_grid(cap);
+        hipLaunchKernelGGL(k_expand, dim3(std::min(blocks, kExpandGrid)), dim3(kWG), 0, st,
+                           t.chunks.as<Chunk>(), t.irec.as<ItemRows>(), t.pos.as<double4>(),
+                           counts, offsets, t.scratch.as<int32_t>(), t.scap, nbrs, t.n,
+                           capacity, t.ctl.as<Ctl>(), cap, blocks);
+        BT_LAUNCH();
+    }
     find_place(t, counts, offsets, nbrs, capacity, st);
     if (time_place) t.timer.stop(kPhPlace, st);
     if (totals) {
@@ -2140,7 +2352,7 @@ void adapt_h_begin(Tree& t, hipStream_t st) {
 
 int64_t adapt_h_step(Tree& t, double* h, const int32_t* counts, double target, double tol,
                      hipStream_t st) {
-    hipLaunchKernelGGL(k_adapt_h, dim3(std::min<unsigned>(grid_for(t.n, 256), 4096u)), dim3(256),
+    hipLaunchKernelGGL(k_adapt_h, dim3(std::min<unsigned>(grid_for(t.n, kWG), 4096u)), dim3(kWG),
                        0, st, counts, h, t.adapt_br.as<double2>(), t.n, target, tol,
                        t.ctl.as<Ctl>());
     BT_LAUNCH();

@@ -66,6 +66,30 @@ def test_plummer_small_full(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_row_paths(prec):
+    """The main sweep's two ways to pass rows to pass 2: test words expanded
+    by k_expand (items whose words take less room than their rows, among
+    them items of more than 8192 row entries, expanded in windows) and rows
+    in the scratch copied by k_place (items of few queries).  With 150
+    neighbours a full item of 64 queries has about 9600 row entries and
+    about 1200 candidates (inside the staging budget), while the short
+    items at the end of leaves keep their rows.  Lists must equal the
+    oracle's."""
+    n = 60_000
+    x, y, z, h = W.uniform_cube(n, 21, 150.0)
+    log("row paths", prec)
+    got = gpu_lists(x, y, z, h, prec, bucket_size=64)
+    want = oracle.lists(x, y, z, h)
+    assert_same_lists(got, want)
+    st = got[3]
+    log("row paths: items", st["n_chunks"], "words", st["word_items"], "wide",
+        st["word_items_wide"], "split", st["split_items"])
+    assert st["word_items_wide"] > 0
+    assert st["word_items"] > st["word_items_wide"]
+    assert st["n_chunks"] - st["word_items"] - st["split_items"] > 0
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_split_paths(prec):
     """Work items whose candidates overflow shared memory: a few queries with
     a larger h make their item's box E too full (the item is re-searched in
