@@ -37,7 +37,10 @@ extern "C" {
 typedef enum {
     BTREE_OK = 0,
     BTREE_EINVAL = -1,     /* bad argument or bad particle data            */
-    BTREE_ENOMEM = -2,     /* a device allocation failed                    */
+    BTREE_ENOMEM = -2,     /* a device allocation failed (for tests, the
+                              environment variable BTREE_FAULT_ALLOC = k
+                              fails the k-th allocation counted from the
+                              last change of its value)                 */
     BTREE_EDEVICE = -3,    /* a HIP runtime call or kernel launch failed    */
     BTREE_EOVERFLOW = -4,  /* caller's output capacity below the total      */
     BTREE_ESTATE = -5      /* call made in a state that does not allow it   */

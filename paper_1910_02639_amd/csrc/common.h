@@ -5,6 +5,8 @@
 #include <stdint.h>
 
 #include <cstdio>
+#include <cstdlib>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -69,6 +71,38 @@ inline void* arena_take(Arena* a, size_t b) {
     return a->base + at;
 }
 
+// hipMalloc behind a fault hook for tests of the allocation-failure paths:
+// while the environment variable BTREE_FAULT_ALLOC holds k >= 1, the k-th
+// device allocation counted from the last change of its value fails with
+// BTREE_ENOMEM (later ones succeed).  Unset or not a positive integer: no
+// effect.
+inline void device_malloc(void** p, size_t b) {
+    static std::mutex mu;
+    static std::string seen;
+    static long long count = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        const char* v = std::getenv("BTREE_FAULT_ALLOC");
+        const std::string now = v ? v : "";
+        if (now != seen) {
+            seen = now;
+            count = 0;
+        }
+        const long long k = v ? std::atoll(v) : 0;
+        if (k > 0 && ++count == k) {
+            *p = nullptr;
+            fail(BTREE_ENOMEM, "device allocation " + std::to_string(k) + " of " +
+                                   std::to_string(b) + " bytes failed by BTREE_FAULT_ALLOC");
+        }
+    }
+    hipError_t e = hipMalloc(p, b);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        fail(e == hipErrorOutOfMemory ? BTREE_ENOMEM : BTREE_EDEVICE,
+             "hipMalloc of " + std::to_string(b) + " bytes: " + hipGetErrorString(e));
+    }
+}
+
 // Device buffer owned by a handle; grows on demand, never shrinks.  While
 // an arena is current on the host thread, memory is carved from it (and
 // `borrowed`: never freed).
@@ -96,12 +130,7 @@ struct DBuf {
             borrowed = true;
             return;
         }
-        hipError_t e = hipMalloc(&p, b);
-        if (e != hipSuccess) {
-            p = nullptr;
-            fail(e == hipErrorOutOfMemory ? BTREE_ENOMEM : BTREE_EDEVICE,
-                 "hipMalloc of " + std::to_string(b) + " bytes: " + hipGetErrorString(e));
-        }
+        device_malloc(&p, b);
         bytes = b;
     }
     // Grows to at least `want` bytes keeping the first `keep` bytes.
@@ -113,10 +142,7 @@ struct DBuf {
         if (a) {
             q = arena_take(a, b);
         } else {
-            hipError_t e = hipMalloc(&q, b);
-            if (e != hipSuccess)
-                fail(e == hipErrorOutOfMemory ? BTREE_ENOMEM : BTREE_EDEVICE,
-                     "hipMalloc of " + std::to_string(b) + " bytes: " + hipGetErrorString(e));
+            device_malloc(&q, b);
         }
         if (p && keep) {
             hipError_t e = hipMemcpyAsync(q, p, keep, hipMemcpyDeviceToDevice, st);

@@ -60,9 +60,12 @@ def test_plummer_small_full(prec):
     log("plummer 30k exhaustive", got[3]["brute_chunks"], "split", got[3]["split_items"])
     # At n = 3e4 the outermost particles have 2h ~ 7 (h grows as rho^-1/3),
     # so their work items see most of the sphere: they are split, and the
-    # queries whose own box is too full take the exhaustive path.
-    assert got[3]["split_items"] > 0
-    assert got[3]["brute_chunks"] < got[3]["n"] // 10
+    # queries whose own box is too full take the exhaustive path.  Measured:
+    # 107 split items; 257 (FP32 filter) and 265 (FP64, whose split budget
+    # is smaller) exhaustive queries.  The bounds hold that with a margin
+    # for the few particles that change work item between builds.
+    assert 0 < got[3]["split_items"] <= 130
+    assert 0 < got[3]["brute_chunks"] <= 320
 
 
 @pytest.mark.parametrize("prec", PRECS)
