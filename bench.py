@@ -95,16 +95,21 @@ def roofline(kernel_ms, tests, ops, kernel, workload):
 
 def hbm_measured(ph, workload):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
-    profiles/traffic.json) over the kernel's time in this run, against the
-    8 TB/s peak.  The placement time is the placement phase as timed (in the
-    batched graph it also holds the exhaustive fill)."""
+    profiles/traffic.json) over the kernels' time in this run, against the
+    8 TB/s peak: the sweep, and the placement (k_expand and k_place, timed
+    together as the placement phase; in the batched graph the phase also
+    holds the exhaustive fill)."""
     out = {}
-    for key, name in (("sweep_kernel", "k_sweep"), ("place_kernel", "k_place")):
-        t = load_traffic(key, workload)
-        if t is None or ph.get(key, 0.0) <= 0.0:
-            continue
-        gbs = t / (ph[key] * 1e-3) / 1e9
-        out[name] = {"hbm_bytes": t, "ms": ph[key], "GB_s": gbs, "frac": gbs / HBM_PEAK_GBS}
+    t = load_traffic("sweep_kernel", workload)
+    if t is not None and ph.get("sweep_kernel", 0.0) > 0.0:
+        gbs = t / (ph["sweep_kernel"] * 1e-3) / 1e9
+        out["k_sweep"] = {"hbm_bytes": t, "ms": ph["sweep_kernel"], "GB_s": gbs,
+                          "frac": gbs / HBM_PEAK_GBS}
+    te, tp = load_traffic("expand_kernel", workload), load_traffic("place_kernel", workload)
+    if te is not None and tp is not None and ph.get("place_kernel", 0.0) > 0.0:
+        gbs = (te + tp) / (ph["place_kernel"] * 1e-3) / 1e9
+        out["k_expand+k_place"] = {"hbm_bytes": te + tp, "ms": ph["place_kernel"], "GB_s": gbs,
+                                   "frac": gbs / HBM_PEAK_GBS}
     return out or None
 
 

@@ -22,6 +22,8 @@ HIPCC_FLAGS = [
     "-ffp-contract=off",
     # Packed FP32 VALU instructions stay disabled.
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # roctx ranges around the phases of the entry points.
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx",
 ]
 
 

@@ -151,6 +151,7 @@ btree_status btree_params_default(btree_params* p) {
 btree_status btree_build(const double* x, const double* y, const double* z, int64_t n,
                          const btree_params* p, void* hip_stream, btree_handle* out) {
     return guarded([&] {
+        Range range("btree_build");
         if (!out) fail(BTREE_EINVAL, "btree_build: out is NULL");
         *out = nullptr;
         btree_params prm;
@@ -178,6 +179,7 @@ btree_status btree_build(const double* x, const double* y, const double* z, int6
 btree_status btree_rebuild(btree_handle H, const double* x, const double* y, const double* z,
                            int64_t n, void* hip_stream) {
     return guarded([&] {
+        Range range("btree_rebuild");
         if (!H) fail(BTREE_ESTATE, "btree_rebuild: NULL handle");
         Tree* t = &H->t;
         check_n(n, x, y, z, t->prm.bucket_size);
@@ -217,6 +219,7 @@ btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* coun
                                 t->p1_offsets == offsets;
         if (nbrs == nullptr || !have_pass1) {
             t->p1_total = -1;
+            Range range("btree_find_neighbors pass 1");
             t->timer.start(kPhPass1, st);
             int64_t tot = find_pass1(*t, h, counts, offsets, st);
             t->timer.stop(kPhPass1, st);
@@ -231,6 +234,7 @@ btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* coun
             if (capacity < t->p1_total)
                 fail(BTREE_EOVERFLOW, "btree_find_neighbors: capacity " + std::to_string(capacity) +
                                           " < total " + std::to_string(t->p1_total));
+            Range range("btree_find_neighbors pass 2");
             t->timer.start(kPhPass2, st);
             find_pass2(*t, h, offsets, nbrs, st);
             t->timer.stop(kPhPass2, st);
@@ -242,6 +246,7 @@ btree_status btree_find_neighbors(btree_handle H, const double* h, int32_t* coun
 btree_status btree_density(btree_handle H, const double* h, const double* mass, double* rho,
                            int32_t* counts, void* hip_stream) {
     return guarded([&] {
+        Range range("btree_density");
         if (!H) fail(BTREE_ESTATE, "btree_density: NULL handle");
         Tree* t = &H->t;
         if (!t->valid) fail(BTREE_ESTATE, "btree_density: the handle holds no tree");
@@ -264,6 +269,7 @@ btree_status btree_density(btree_handle H, const double* h, const double* mass, 
 btree_status btree_adapt_h(btree_handle H, double* h, double target, double tol, int32_t max_iter,
                            int32_t* counts, int32_t* iterations, void* hip_stream) {
     return guarded([&] {
+        Range range("btree_adapt_h");
         if (!H) fail(BTREE_ESTATE, "btree_adapt_h: NULL handle");
         Tree* t = &H->t;
         if (!t->valid) fail(BTREE_ESTATE, "btree_adapt_h: the handle holds no tree");
@@ -371,6 +377,7 @@ btree_status btree_find_neighbors_noalloc(const double* x, const double* y, cons
                                           int32_t* counts, int64_t* offsets, int32_t* nbrs,
                                           int64_t capacity, int64_t* total, void* hip_stream) {
     return guarded([&] {
+        Range range("btree_find_neighbors_noalloc");
         if (!total) fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: total is NULL");
         if (n < 0 || n > BTREE_NOALLOC_MAX_N)
             fail(BTREE_EINVAL, "btree_find_neighbors_noalloc: n = " + std::to_string(n) +

@@ -290,6 +290,7 @@ btree_status btree_batch_run(btree_batch_handle H, const double* x, const double
                              int32_t* nbrs, int64_t capacity, int64_t* totals, int64_t* total,
                              void* hip_stream) {
     return guarded_b([&] {
+        Range range("btree_batch_run");
         if (!H) fail(BTREE_ESTATE, "btree_batch_run: NULL handle");
         Batch& B = H->b;
         Tree& t = B.t;
@@ -386,6 +387,7 @@ btree_status btree_tune(const double* x, const double* y, const double* z, const
                         int64_t n, const btree_params* base, const btree_tune_space* space,
                         btree_params* best, double* best_ms, double* all_ms, void* hip_stream) {
     return guarded_b([&] {
+        Range range("btree_tune");
         if (!best || !best_ms) fail(BTREE_EINVAL, "btree_tune: NULL best or best_ms");
         btree_params prm;
         if (base) prm = *base;

@@ -10,6 +10,8 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "btree.h"
 
 namespace bt {
@@ -42,6 +44,15 @@ struct Fail {
             throw ::bt::Fail{BTREE_EDEVICE};                                 \
         }                                                                    \
     } while (0)
+
+// A named roctx range over a scope (a phase of an entry point), seen by
+// rocprofv3 --marker-trace; inert when no tool is attached.
+struct Range {
+    explicit Range(const char* name) { roctxRangePushA(name); }
+    ~Range() { roctxRangePop(); }
+    Range(const Range&) = delete;
+    Range& operator=(const Range&) = delete;
+};
 
 [[noreturn]] inline void fail(btree_status code, const std::string& msg) {
     set_error(msg);
