@@ -54,7 +54,8 @@ __global__ void k_ctl_reset(Ctl* __restrict__ ctl) {
     }
 }
 
-// A1: validate coordinates, original-order copy, bounding-box partials per tile.
+// A1: validate coordinates, original-order copy (.w = the particle's index),
+// bounding-box partials per tile.
 __global__ __launch_bounds__(kT) void k_ingest(const double* __restrict__ x,
                                                const double* __restrict__ y,
                                                const double* __restrict__ z,
@@ -68,7 +69,7 @@ __global__ __launch_bounds__(kT) void k_ingest(const double* __restrict__ x,
     for (int64_t i = T.beg + threadIdx.x; i < T.end; i += kT) {
         const double a = x[i], b = y[i], c = z[i];
         bad |= !(isfinite(a) && isfinite(b) && isfinite(c));
-        orig[i] = make_double4(a, b, c, 0.0);
+        orig[i] = make_double4(a, b, c, (double)i);  // .w: the index, as in the tree copy
         mn[0] = fmin(mn[0], a); mx[0] = fmax(mx[0], a);
         mn[1] = fmin(mn[1], b); mx[1] = fmax(mx[1], b);
         mn[2] = fmin(mn[2], c); mx[2] = fmax(mx[2], c);

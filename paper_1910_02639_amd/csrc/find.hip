@@ -585,13 +585,13 @@ __device__ __forceinline__ double sph_shape(double d2, double h) {
 // m_j w(r_ij / h_i) of one neighbour j (key = its original index) of the
 // query at (x, y, z) with smoothing length h, from FP64 coordinates.
 __device__ __forceinline__ double sph_term(double x, double y, double z, double h, int key,
-                                           const double4* __restrict__ orig,
+                                           const double4* __restrict__ src,
                                            const double* __restrict__ mass) {
-    const double4 o = orig[key];
+    const double4 o = src[key];  // either particle copy: .w is the original index
     const double dx = __dsub_rn(x, o.x), dy = __dsub_rn(y, o.y), dz = __dsub_rn(z, o.z);
     const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
     const double w = sph_shape(d2, h);
-    return mass ? __dmul_rn(mass[key], w) : w;
+    return mass ? __dmul_rn(mass[(int)o.w], w) : w;
 }
 
 // Density from the sum of the terms of a row: sum / (pi h^3); 0 for an
@@ -629,6 +629,14 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     // the caller's CSR once the offsets are known; the split levels write
     // rows to the scratch (k_place copies them).
     constexpr bool kBits = OUT == kOutRows && WALK == 1 && !SMALL;
+    // The density form never lists indices: its entries carry the tree
+    // position instead of the original index, so the coordinates of a term
+    // (and of an FP64 confirmation) come from the tree-ordered copy, whose
+    // entries for one item lie in a few nearby leaves, not from scattered
+    // places in the caller's order.  Candidates are then ordered by tree
+    // position (the sum's order, fixed for a given tree).
+    constexpr bool kTreeKeys = OUT == kOutDensity;
+    const double4* __restrict__ const src = kTreeKeys ? pos : orig;
     constexpr int kMaxW = ((CMAX / kWaves) + 31) / 32;  // bit words per lane and wavefront
     __shared__ E s_cand[CMAX];
     __shared__ int32_t s_cnt[kWaves][64];
@@ -666,6 +674,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     const bool qv = lane < ch.cnt;
     const double4 qp = qv ? pos[ch.beg + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
     const int qidx = (int)qp.w;
+    const int qkey = kTreeKeys ? ch.beg + lane : qidx;  // the query's own entry
     const double R = qv ? 2.0 * h[ch.beg + lane] : 0.0;
 
     // Box E of the item and the filter's item-wide bounds: from the walk
@@ -771,7 +780,11 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     const int kmin = __builtin_amdgcn_readfirstlane(s_kmin);
     const int kmax = __builtin_amdgcn_readfirstlane(s_kmax);
     // Buckets of the original index: a monotone map of [kmin, kmax] onto
-    // 0..255, so sorting each bucket sorts the whole candidate list.
+    // 0..255, so sorting each bucket sorts the whole candidate list.  The
+    // density form's keys (tree positions) cluster in the few leaves of the
+    // item, so there a multiplicative hash spreads them over the buckets:
+    // the order is then fixed for a given tree, not ascending, which is all
+    // the sum needs.
     const float binv = (float)kBuckets / (float)((int64_t)kmax - kmin + 1);
 
     // (first particle, count) of candidate leaf li.
@@ -789,6 +802,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         int2 L = li < nleaf ? leaf_at(li) : make_int2(0, 0);
         bool vn = li < nleaf && lane < L.y;
         double4 Pn = vn ? pos[L.x + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+        if (kTreeKeys) Pn.w = (double)(L.x + lane);
         while (li < nleaf) {
             const double4 P = Pn;
             const bool v = vn;
@@ -800,6 +814,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
             }
             vn = li < nleaf && p0 + lane < L.y;
             Pn = vn ? pos[L.x + p0 + lane] : make_double4(0.0, 0.0, 0.0, 0.0);
+            if (kTreeKeys) Pn.w = (double)(L.x + p0 + lane);
             const bool in = v && P.x >= elo[0] && P.x <= ehi[0] && P.y >= elo[1] &&
                             P.y <= ehi[1] && P.z >= elo[2] && P.z <= ehi[2];
             body(P, in);
@@ -813,7 +828,11 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         else
             return P;
     };
-    auto bucket = [&](int key) { return min(kBuckets - 1, (int)((float)(key - kmin) * binv)); };
+    auto bucket = [&](int key) -> int {
+        if constexpr (kTreeKeys) return (int)(((uint32_t)key * 2654435761u) >> 24);
+        else return min(kBuckets - 1, (int)((float)(key - kmin) * binv));
+    };
+    static_assert(kBuckets == 256, "the hash takes the top 8 bits");
     constexpr int kPer = (CMAX + kWG - 1) / kWG;
     constexpr bool kPhys = kPer <= 6;  // six entries per thread fit in registers
 
@@ -901,7 +920,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         // Rank of entry e from slot p (or -1 past the list).
         auto rank_of = [&](int p, const E e) -> int {
             const int key = Ent<F32>::key(e);
-            const int bk = min(kBuckets - 1, (int)((float)(key - kmin) * binv));
+            const int bk = bucket(key);
             const int b1 = p < C ? s_bcur[bk] : 0;
             int r = s_bcnt[bk];
             for (int q = r; q < b1; ++q) r += Ent<F32>::key(s_cand[q]) < key;
@@ -930,7 +949,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     } else if (!s_big) {
         for (int p = t; p < C; p += kWG) {
             const int key = Ent<F32>::key(s_cand[p]);
-            const int bk = min(kBuckets - 1, (int)((float)(key - kmin) * binv));
+            const int bk = bucket(key);
             const int b1 = s_bcur[bk];
             int r = s_bcnt[bk];
             for (int q = r; q < b1; ++q) r += Ent<F32>::key(s_cand[q]) < key;
@@ -984,7 +1003,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     auto query = [&](int q) -> Q {
         return Q{__shfl(qp.x, q, 64), __shfl(qp.y, q, 64), __shfl(qp.z, q, 64), __shfl(R, q, 64),
                  __shfl(r2q, q, 64),  __shfl(ax, q, 64),   __shfl(ay, q, 64),   __shfl(az, q, 64),
-                 __shfl(tlo, q, 64),  __shfl(thi, q, 64),  __shfl(qidx, q, 64)};
+                 __shfl(tlo, q, 64),  __shfl(thi, q, 64),  __shfl(qkey, q, 64)};
     };
     // Hits of query Qd among chunk c.
     auto chunk_hits = [&](const Q& Qd, int c, unsigned long long& nconf) -> uint64_t {
@@ -1000,7 +1019,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 nconf += __popcll(band);
                 bool ok = false;
                 if ((band >> lane) & 1) {
-                    const double4 o = orig[Ent<F32>::key(e)];
+                    const double4 o = src[Ent<F32>::key(e)];
                     ok = p64(Qd.x, Qd.y, Qd.z, Qd.R, o.x, o.y, o.z);
                 }
                 lo |= __ballot(ok);
@@ -1057,7 +1076,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                     double term = 0.0;
                     if ((m >> lane) & 1)
                         term = sph_term(Qd.x, Qd.y, Qd.z, 0.5 * Qd.R,
-                                        Ent<F32>::key(cand(c * 64 + lane)), orig, dout.mass);
+                                        Ent<F32>::key(cand(c * 64 + lane)), src, dout.mass);
                     dq += wave_sum(term);
                 }
             }
@@ -1115,7 +1134,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                             bit = 0u;
                         } else {
                             ++lconf;
-                            const double4 o = orig[__float_as_int(e.w)];
+                            const double4 o = src[__float_as_int(e.w)];
                             bit = p64(qp.x, qp.y, qp.z, R, o.x, o.y, o.z) ? 1u : 0u;
                         }
                         nwd = (nwd << 1) | bit;
@@ -1168,15 +1187,28 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     // exclude_self: the query's own bit is cleared before anything is
     // counted, so counts, row offsets and rows all leave it out.  The query
     // lies inside its item's box, so it is one of the candidates; its place
-    // in the index-ordered list is found by bisection on the keys.
+    // in the ordered list is found by bisection on the keys, or (hashed
+    // buckets of the density form) by a scan of its own bucket, whose range
+    // the ordering kept.
     if (excl && !small && qv && r2q > 0.0 && C > 0) {
-        int lo = 0, hi = C - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (Ent<F32>::key(cand(mid)) < qidx) lo = mid + 1;
-            else hi = mid;
+        int lo = 0;
+        if (kTreeKeys && !s_big) {
+            const int b = bucket(qkey);
+            lo = s_bcur[b];
+            for (int q = s_bcnt[b]; q < s_bcur[b]; ++q)
+                if (Ent<F32>::key(cand(q)) == qkey) {
+                    lo = q;
+                    break;
+                }
+        } else {
+            int hi = C - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (Ent<F32>::key(cand(mid)) < qkey) lo = mid + 1;
+                else hi = mid;
+            }
         }
-        if (lo >= k0 && lo < k1 && Ent<F32>::key(cand(lo)) == qidx) {
+        if (lo >= k0 && lo < k1 && Ent<F32>::key(cand(lo)) == qkey) {
             const int slot = kMaxW - nw + ((lo - k0) >> 5);
             const uint32_t bit = 0x80000000u >> ((lo - k0) & 31);
 #pragma unroll
@@ -1195,7 +1227,8 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
         if (!small) {
             // Each neighbour's coordinates (and mass) are loaded one hit
             // ahead of their use, so a load is in flight while the previous
-            // term is evaluated.
+            // term is evaluated; the coordinates come from the tree-ordered
+            // copy (the entries' keys are tree positions).
             double acc = 0.0;
             const int wbase = kMaxW - nw;
             const double hq = 0.5 * R;
@@ -1208,18 +1241,16 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                     double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
                     double mj = 1.0;
                     if (word) {
-                        const int key = Ent<F32>::key(cand(kb + __clz(word)));
-                        o = orig[key];
-                        if (dout.mass) mj = dout.mass[key];
+                        o = src[Ent<F32>::key(cand(kb + __clz(word)))];
+                        if (dout.mass) mj = dout.mass[(int)o.w];
                     }
                     while (word) {
                         word &= ~(0x80000000u >> __clz(word));
                         double4 on = o;
                         double mn = mj;
                         if (word) {
-                            const int key = Ent<F32>::key(cand(kb + __clz(word)));
-                            on = orig[key];
-                            if (dout.mass) mn = dout.mass[key];
+                            on = src[Ent<F32>::key(cand(kb + __clz(word)))];
+                            if (dout.mass) mn = dout.mass[(int)on.w];
                         }
                         const double dx = __dsub_rn(qp.x, o.x), dy = __dsub_rn(qp.y, o.y);
                         const double dz = __dsub_rn(qp.z, o.z);
