@@ -418,15 +418,17 @@ def bench_build_sweep(name, buckets=(16, 32, 64, 128, 256), betas=(0.3, 0.5, 0.8
     return {"workload": name, "build_ms": table, "depth": depth}
 
 
-def bench_density_and_adapt(name, steps=5):
+def bench_density_and_adapt(name, tuner, steps=5):
     """The fused density (no lists) against the lists (both passes), and the
-    h adaptation from 0.7 h to the workload's target count."""
+    h adaptation from 0.7 h to the workload's target count, on the tree of
+    the single-set timing's (tuned) parameters."""
     import torch
     from paper_1910_02639_amd import btree, workloads as W
     x, y, z, h, s_ = W.make(name)
     n = len(x)
     dx, dy, dz, dh = (torch.from_numpy(v).to("cuda:0") for v in (x, y, z, h))
-    t = btree.BTree(dx, dy, dz, bucket_size=s_)
+    prm = tuner.params_for(dx, dy, dz, dh, "fp32")
+    t = btree.BTree(dx, dy, dz, **prm)
     counts = torch.empty(n, dtype=torch.int32, device="cuda:0")
     offsets = torch.empty(n + 1, dtype=torch.int64, device="cuda:0")
     rho = torch.empty(n, dtype=torch.float64, device="cuda:0")
@@ -456,7 +458,7 @@ def bench_density_and_adapt(name, steps=5):
     within = float(((c.to(torch.float64) - target).abs() <= 3.0).double().mean())
     t.close()
     log("density and h adaptation", name, "done")
-    return {"workload": name, "n": n, "density_ms": dens_ms, "lists_ms": lists_ms,
+    return {"workload": name, "n": n, "params": prm, "density_ms": dens_ms, "lists_ms": lists_ms,
             "density_vs_lists_speedup": lists_ms / dens_ms,
             "adapt_h": {"from": "0.7 h", "target": target, "tol": 3.0, "rounds": rounds,
                         "ms": adapt_ms, "ms_per_round": adapt_ms / max(rounds + 1, 1),
@@ -519,7 +521,7 @@ def main():
                     "P8M": bench_octree_single("P8M", tuner),
                     "L1M": bench_octree_single("L1M", tuner)}
                 out["build_sweep_P8M"] = bench_build_sweep("P8M")
-                out["sph_P8M"] = bench_density_and_adapt("P8M")
+                out["sph_P8M"] = bench_density_and_adapt("P8M", tuner)
             for name in ("L1M", "U10k"):
                 r, _ = bench_single(name, "fp32", max(2, min(a.steps, 10)), 2, not a.no_compare,
                                     tuner)
