@@ -126,6 +126,24 @@ def roofline_hbm(n, total, kernel_ms, workload):
             "traffic_ratio": (t / alg) if t else None}
 
 
+def pair_rates(tests, step_ms, sweep_ms):
+    """Pair tests per second over the whole step and over the sweep kernel."""
+    return {"per_step": tests / (step_ms * 1e-3),
+            "sweep_kernel": tests / (sweep_ms * 1e-3) if sweep_ms > 0 else None}
+
+
+# The paper's own figures (CPU only; context, not a target): one Intel Xeon
+# E5-2640 v4 node, 20 cores + 20 hyper-threads, 40 OpenMP threads (Table 2).
+PAPER_CONTEXT = {
+    "hardware": "Intel Xeon E5-2640 v4, 20 cores (40 threads), CPU only (Table 2)",
+    "btree_vs_octree": {"find_neighbors": "up to 1.6x faster", "build_tree": "up to 12x faster"},
+    "find_neighbors_s": {"evrard_collapse_1e6_100nb": 0.15, "square_patch_1e7_500nb": 4.0},
+    "derived_particles_per_s": {"evrard_collapse": 6.7e6, "square_patch": 2.5e6},
+    "note": "Section 4 prose (the figures are not in the source); the GPU workloads here are "
+            "synthetic stand-ins, so no ratio to these is reported",
+}
+
+
 def search_hbm(n, total, search_ms):
     # Compulsory HBM bytes of the whole search (both passes), per particle:
     # coordinates 24 B + h 8 B + count 4 B + offset 8 B, plus 4 B per entry.
@@ -183,6 +201,7 @@ def bench_single(name, precision, steps, warmup, compare, tuner, bucket=0):
     out = {"workload": name, "n": n, "params": prm, "value": n * steps / el,
            "ms_per_step": 1e3 * el / steps, "phases_ms": ph,
            "neighbours_total": total, "pair_tests_per_particle": st["pair_tests"] / n,
+           "pair_tests_per_s": pair_rates(st["pair_tests"], 1e3 * el / steps, ph["sweep_kernel"]),
            "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, st["pair_tests"]),
            "exhaustive_items": st["brute_chunks"],
            "exhaustive_units": st["brute_units"], "split_items": st["split_items"],
@@ -198,10 +217,12 @@ def bench_single(name, precision, steps, warmup, compare, tuner, bucket=0):
         p64 = tuner.params_for(dx, dy, dz, dh, "fp64") if not bucket else prm
         t2 = btree.BTree(dx, dy, dz, precision="fp64", timing=True, **p64)
         k2 = max(2, min(steps, 5))
-        el2, ph2, _ = single_timed(t2, args, k2, 1)
+        el2, ph2, st2 = single_timed(t2, args, k2, 1)
         t2.close()
         out["fp64_plain"] = {"value": n * k2 / el2, "ms_per_step": 1e3 * el2 / k2,
-                             "params": p64, "search_ms": ph2["pass1"] + ph2["pass2"], "steps": k2}
+                             "params": p64, "search_ms": ph2["pass1"] + ph2["pass2"], "steps": k2,
+                             "pair_tests_per_s": pair_rates(st2["pair_tests"], 1e3 * el2 / k2,
+                                                           ph2["sweep_kernel"])}
         out["fp32_filter_speedup"] = out["value"] / out["fp64_plain"]["value"]
     return out, (x, y, z, h)
 
@@ -295,10 +316,12 @@ def bench_batch(a, tuner):
         "phases_ms": ph,
         "search_particles_per_s": n / ((ph["pass1"] + ph["pass2"]) * 1e-3),
         "pair_tests_per_particle": st["pair_tests"] / n,
+        "pair_tests_per_s": pair_rates(st["pair_tests"], 1e3 * el / a.steps, ph["sweep_kernel"]),
         "fp64_confirmed_fraction": st["fp64_confirms"] / max(1, st["pair_tests"]),
         "exhaustive_items": st["brute_chunks"],
         "exhaustive_units": st["brute_units"], "split_items": st["split_items"],
         "graph": {"launches": st["graph_launches"], "recordings": st["graph_captures"]},
+        "paper_context": PAPER_CONTEXT,
         "tree": {"depth": st["depth"], "internal": st["n_internal"], "leaves": st["n_leaves"]},
         "roofline": roofline(ph["sweep_kernel"], st["pair_tests"], OPS_PER_TEST_F32,
                              "k_sweep<fp32>", "Batch64"),
