@@ -304,8 +304,9 @@ btree_status btree_batch_graph_counts(btree_batch_handle b, int64_t* launches,
 btree_status btree_batch_destroy(btree_batch_handle b);
 
 /* ------------------------------------------------------------------------
- * Autotuning of s and beta (the parameters of Table 1 and Eq. 4).  Results
- * do not depend on the parameters, so a tuner can only change speed.
+ * Autotuning of s, beta and alpha (the parameters of Table 1 and Eq. 4:
+ * the bucket size and the empty-cell limit).  Results do not depend on the
+ * parameters, so a tuner can only change speed.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t n_bucket;       /* candidate bucket sizes s, 1..16              */
@@ -313,20 +314,25 @@ typedef struct {
     int32_t n_beta;         /* candidate beta values, 1..8                  */
     double  beta[8];
     int32_t repeats;        /* timed runs per candidate (median), 1..100   */
-    int32_t reserved[3];    /* must be zero                                 */
+    int32_t n_alpha;        /* candidate alpha values, 0..4 (0: the base
+                               parameters' alpha only)                       */
+    double  alpha[4];       /* finite and >= 0                               */
+    int32_t reserved[2];    /* must be zero                                 */
 } btree_tune_space;
 
 /* Default space: s in {16, 24, 32, 48, 64, 96, 128, 192, 256}, beta in
- * {0.3, 0.5, 0.8}, 3 repeats.  Errors: EINVAL (NULL). */
+ * {0.3, 0.5, 0.8}, alpha in {0.25, 0.5, 1}, 3 repeats.
+ * Errors: EINVAL (NULL). */
 btree_status btree_tune_space_default(btree_tune_space* space);
 
 /* Times BuildTree + both FindNeighbors passes on the given particles for
- * every (s, beta) of `space` (NULL = default), other parameters from `base`
+ * every (s, beta, alpha) of `space` (NULL = default), other parameters from `base`
  * (NULL = defaults): the device time of the recorded graph of a one-set
  * batch (HIP events around its launch on hip_stream, so host round trips
  * of the eager path do not count), and returns in *best the parameters of
  * the fastest median and in *best_ms that median.
- * all_ms: HOST double[n_bucket * n_beta] (row-major by bucket) or NULL.
+ * all_ms: HOST double[n_bucket * n_beta * max(n_alpha, 1)] (row-major:
+ *   bucket, then beta, then alpha) or NULL.
  * Allocates its own device buffers; synchronises the stream.
  * Errors: EINVAL (bad arguments or data), ENOMEM, EDEVICE. */
 btree_status btree_tune(const double* x, const double* y, const double* z,

@@ -32,7 +32,8 @@ CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.jso
 class TuneSpace(ctypes.Structure):
     _fields_ = [("n_bucket", ctypes.c_int32), ("bucket", ctypes.c_int32 * 16),
                 ("n_beta", ctypes.c_int32), ("beta", ctypes.c_double * 8),
-                ("repeats", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("repeats", ctypes.c_int32), ("n_alpha", ctypes.c_int32),
+                ("alpha", ctypes.c_double * 4), ("reserved", ctypes.c_int32 * 2)]
 
 
 def _lib():
@@ -49,9 +50,13 @@ def _lib():
     return L
 
 
-def space(buckets=None, betas=None, repeats=None) -> TuneSpace:
+def space(buckets=None, betas=None, repeats=None, alphas=None) -> TuneSpace:
     sp = TuneSpace()
     btree._check(_lib().btree_tune_space_default(ctypes.byref(sp)))
+    if alphas is not None:
+        sp.n_alpha = len(alphas)
+        for k, a in enumerate(alphas):
+            sp.alpha[k] = float(a)
     if buckets is not None:
         sp.n_bucket = len(buckets)
         for k, b in enumerate(buckets):
@@ -87,14 +92,17 @@ def tune(x, y, z, h, precision="fp32", sp: TuneSpace | None = None, stream=None)
     sp = sp if sp is not None else space()
     best = btree.Params()
     best_ms = ctypes.c_double()
-    table = np.zeros(sp.n_bucket * sp.n_beta, dtype=np.float64)
+    na = max(sp.n_alpha, 1)
+    table = np.zeros(sp.n_bucket * sp.n_beta * na, dtype=np.float64)
     btree._check(_lib().btree_tune(ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
                                    ctypes.c_void_p(z.data_ptr()), ctypes.c_void_p(h.data_ptr()),
                                    n, ctypes.byref(base), ctypes.byref(sp), ctypes.byref(best),
                                    ctypes.byref(best_ms), table.ctypes.data,
                                    btree._stream(stream)))
-    grid = {"%d/%g" % (sp.bucket[i], sp.beta[j]): float(table[i * sp.n_beta + j])
-            for i in range(sp.n_bucket) for j in range(sp.n_beta)}
+    alphas = [sp.alpha[k] for k in range(sp.n_alpha)] or [float(base.alpha)]
+    grid = {"%d/%g/%g" % (sp.bucket[i], sp.beta[j], alphas[a]):
+            float(table[(i * sp.n_beta + j) * na + a])
+            for i in range(sp.n_bucket) for j in range(sp.n_beta) for a in range(na)}
     return {"bucket_size": int(best.bucket_size), "beta": float(best.beta),
             "alpha": float(best.alpha), "ms": float(best_ms.value), "n": n, "table": grid}
 
@@ -147,8 +155,9 @@ class Tuner:
         if not self.fresh(k):
             can = self.tune_missing and (self.budget_s is None or self.spent_s < self.budget_s)
             if can:
+                sp = self.sp if self.sp is not None else space()
                 self._log("tuning %s (n = %d, %d candidates)" % (
-                    k, n, (self.sp.n_bucket * self.sp.n_beta) if self.sp else 27))
+                    k, n, sp.n_bucket * sp.n_beta * max(sp.n_alpha, 1)))
                 t0 = time.perf_counter()
                 e = tune(x, y, z, h, precision, self.sp)
                 dt = time.perf_counter() - t0
@@ -157,8 +166,8 @@ class Tuner:
                 e["tune_s"] = dt
                 self.entries[k] = e
                 self.tuned_now.append(k)
-                self._log("tuned %s: s = %d, beta = %g, %.3f ms (%.1f s)" % (
-                    k, e["bucket_size"], e["beta"], e["ms"], dt))
+                self._log("tuned %s: s = %d, beta = %g, alpha = %g, %.3f ms (%.1f s)" % (
+                    k, e["bucket_size"], e["beta"], e["alpha"], e["ms"], dt))
             elif k in self.entries:
                 if k not in self.stale_used:
                     self.stale_used.append(k)

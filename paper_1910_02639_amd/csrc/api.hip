@@ -444,6 +444,9 @@ btree_status btree_tune_space_default(btree_tune_space* sp) {
     const double b[] = {0.3, 0.5, 0.8};
     sp->n_beta = 3;
     for (int k = 0; k < 3; ++k) sp->beta[k] = b[k];
+    const double a[] = {0.25, 0.5, 1.0};
+    sp->n_alpha = 3;
+    for (int k = 0; k < 3; ++k) sp->alpha[k] = a[k];
     sp->repeats = 3;
     set_error("");
     return BTREE_OK;

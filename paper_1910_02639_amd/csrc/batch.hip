@@ -398,8 +398,9 @@ btree_status btree_tune(const double* x, const double* y, const double* z, const
         if (space) sp = *space;
         else btree_tune_space_default(&sp);
         if (sp.n_bucket < 1 || sp.n_bucket > 16 || sp.n_beta < 1 || sp.n_beta > 8 || sp.repeats < 1 ||
-            sp.repeats > 100)
-            fail(BTREE_EINVAL, "btree_tune: space needs 1..16 buckets, 1..8 betas, 1..100 repeats");
+            sp.repeats > 100 || sp.n_alpha < 0 || sp.n_alpha > 4)
+            fail(BTREE_EINVAL,
+                 "btree_tune: space needs 1..16 buckets, 1..8 betas, 0..4 alphas, 1..100 repeats");
         if (n < 0 || n >= 0x7fffffffll) fail(BTREE_EINVAL, "btree_tune: n must be in [0, 2^31-1)");
         for (int k = 0; k < sp.n_bucket; ++k) {
             btree_params q = prm;
@@ -410,8 +411,13 @@ btree_status btree_tune(const double* x, const double* y, const double* z, const
         }
         for (int k = 0; k < sp.n_beta; ++k)
             if (!std::isfinite(sp.beta[k])) fail(BTREE_EINVAL, "btree_tune: beta must be finite");
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < sp.n_alpha; ++k)
+            if (!std::isfinite(sp.alpha[k]) || sp.alpha[k] < 0.0)
+                fail(BTREE_EINVAL, "btree_tune: alpha must be finite and >= 0");
+        for (int k = 0; k < 2; ++k)
             if (sp.reserved[k] != 0) fail(BTREE_EINVAL, "btree_tune: reserved fields must be zero");
+        // No alpha listed: the base parameters' alpha is the only candidate.
+        const int na = sp.n_alpha > 0 ? sp.n_alpha : 1;
         if (n > 0 && (!x || !y || !z || !h)) fail(BTREE_EINVAL, "btree_tune: NULL particle array");
         *best = prm;
         *best_ms = 0.0;
@@ -427,10 +433,12 @@ btree_status btree_tune(const double* x, const double* y, const double* z, const
         const int64_t off[2] = {0, n};
         double best_t = INFINITY;
         for (int kb = 0; kb < sp.n_bucket; ++kb) {
-            for (int kt = 0; kt < sp.n_beta; ++kt) {
+            for (int kc = 0; kc < sp.n_beta * na; ++kc) {
+                const int kt = kc / na, ka = kc % na;
                 btree_params q = prm;
                 q.bucket_size = sp.bucket[kb];
                 q.beta = sp.beta[kt];
+                if (sp.n_alpha > 0) q.alpha = sp.alpha[ka];
                 // Device time of the recorded graph (build + both search
                 // passes), as the batched form runs it: no host round trips.
                 Batch B;
@@ -448,7 +456,7 @@ btree_status btree_tune(const double* x, const double* y, const double* z, const
                 }
                 std::sort(ms.begin(), ms.end());
                 const double med = ms[ms.size() / 2];
-                if (all_ms) all_ms[kb * sp.n_beta + kt] = med;
+                if (all_ms) all_ms[(int64_t)kb * sp.n_beta * na + kc] = med;
                 if (med < best_t) {
                     best_t = med;
                     *best = q;

@@ -300,14 +300,16 @@ def test_tuner_picks_a_candidate_and_results_do_not_depend_on_it():
     from paper_1910_02639_amd import autotune, btree
     x, y, z, h = W.uniform_cube(8000, 9, 40.0)
     dx, dy, dz, dh = to_dev(x, y, z, h)
-    sp = autotune.space(buckets=[16, 64], betas=[0.5, 0.8], repeats=2)
+    sp = autotune.space(buckets=[16, 64], betas=[0.5, 0.8], repeats=2, alphas=[0.25, 1.0])
     r = autotune.tune(dx, dy, dz, dh, "fp32", sp)
-    assert r["bucket_size"] in (16, 64) and r["beta"] in (0.5, 0.8)
+    assert r["bucket_size"] in (16, 64) and r["beta"] in (0.5, 0.8) and r["alpha"] in (0.25, 1.0)
+    assert len(r["table"]) == 8
     assert r["ms"] > 0 and all(v > 0 for v in r["table"].values())
     assert r["ms"] == min(r["table"].values())
+    assert r["table"]["%d/%g/%g" % (r["bucket_size"], r["beta"], r["alpha"])] == r["ms"]
     want = oracle.lists(x, y, z, h)
-    for s in (16, 64):
-        with btree.Batch([len(x)], bucket_size=s, beta=r["beta"]) as B:
+    for s, a in ((16, 0.25), (64, 1.0)):
+        with btree.Batch([len(x)], bucket_size=s, beta=r["beta"], alpha=a) as B:
             c, o, nb, totals = B.find(dx, dy, dz, dh)
             _check_batch([(x, y, z, h)], *_host(c, o, nb), totals)
     assert want[1][-1] == totals[0]

@@ -185,6 +185,7 @@ def test_tune_space_and_argument_checks(L):
     sp = autotune.space()
     assert list(sp.bucket)[:sp.n_bucket] == [16, 24, 32, 48, 64, 96, 128, 192, 256]
     assert list(sp.beta)[:sp.n_beta] == [0.3, 0.5, 0.8]
+    assert list(sp.alpha)[:sp.n_alpha] == [0.25, 0.5, 1.0]
     lib = autotune._lib()
     assert lib.btree_tune_space_default(None) == L.BTREE_EINVAL
     best = L.Params()
@@ -194,6 +195,13 @@ def test_tune_space_and_argument_checks(L):
     assert lib.btree_tune(P, P, P, P, 10, None, None, None, ctypes.byref(ms), None, None) \
         == L.BTREE_EINVAL
     bad = autotune.space(repeats=0)
+    assert lib.btree_tune(P, P, P, P, 10, None, ctypes.byref(bad), ctypes.byref(best),
+                          ctypes.byref(ms), None, None) == L.BTREE_EINVAL
+    bad = autotune.space(alphas=[0.5, -0.1])
+    assert lib.btree_tune(P, P, P, P, 10, None, ctypes.byref(bad), ctypes.byref(best),
+                          ctypes.byref(ms), None, None) == L.BTREE_EINVAL
+    bad = autotune.space()
+    bad.n_alpha = 5
     assert lib.btree_tune(P, P, P, P, 10, None, ctypes.byref(bad), ctypes.byref(best),
                           ctypes.byref(ms), None, None) == L.BTREE_EINVAL
     bad = autotune.space(buckets=[16, 0])
