@@ -3,8 +3,9 @@
 // Work item: up to 64 consecutive particles of one leaf (the paper's
 // blocked, cache-reusing search, recast for a GPU: a leaf's particles share
 // one tree walk and one staged candidate set).  Pass 1 writes every query's
-// count and its row to a scratch buffer; pass 2 places the rows into the
-// caller's CSR arrays once the offsets are known.
+// count and keeps each item's result in a scratch buffer (its test words and
+// ordered candidates, or its rows, whichever is smaller); pass 2 puts the
+// rows into the caller's CSR arrays once the offsets are known.
 //
 //  1. k_walk, one wavefront per item: box E = [min_i fl(x_i - 2h_i),
 //     max_i fl(x_i + 2h_i)]; walk (Algorithm 2 with Eq. 5 applied to E),
@@ -18,13 +19,16 @@
 //     lie inside E are staged into LDS (every true neighbour of every query
 //     lies inside E) and put in original index order; wavefront w sweeps
 //     its quarter of them for its 64 queries (LDS reads broadcast to all
-//     lanes), one bit per (query, candidate); each lane then writes its row
-//     in ascending index to the scratch.
+//     lanes), one bit per (query, candidate); the item then stores its
+//     words and candidates, or each lane writes its row in ascending index,
+//     to the scratch.
 //  3. Items whose candidates do not fit the LDS budget are searched again
 //     by k_sweep_split (the whole item with a larger budget, then parts of
 //     8 queries, then single queries), and what still does not fit by an
 //     exhaustive FP64 sweep of the query's set in index order (k_dense).
-//  4. k_place copies the rows into the CSR arrays (pass 2).
+//  4. Pass 2: k_expand expands the items' words into the CSR rows (through
+//     a shared-memory image of each item's rows, copied out row by row);
+//     k_place copies the rows kept in the scratch.
 //
 // Two arithmetic forms of the pair test, with identical results:
 //  * FP64: the exact predicate ((dx*dx + dy*dy) + dz*dz) < (2h)*(2h).
@@ -1580,9 +1584,10 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
 // destination) and copies them four at a time with all its lanes, so every
 // load and store is coalesced and no lane searches for its row; the first
 // 128 entries of the four rows are loaded before any is stored, so that
-// eight loads per lane are in flight.  Rows taken by the exhaustive path
-// (or without room in the scratch) count as empty here.  Nothing is written
-// when the rows do not fit the caller's capacity.
+// eight loads per lane are in flight.  Rows taken by the exhaustive path,
+// rows that k_expand writes from an item's words and rows without room in
+// the scratch (soff < 0) count as empty here.  Nothing is written when the
+// rows do not fit the caller's capacity.
 __device__ __forceinline__ int64_t readlane64(int64_t v, int j) {
     const int lo = __builtin_amdgcn_readlane((int)(uint32_t)v, j);
     const int hi = __builtin_amdgcn_readlane((int)(v >> 32), j);
