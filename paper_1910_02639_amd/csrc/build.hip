@@ -1297,17 +1297,26 @@ void build_queue(Tree& t, const double* x, const double* y, const double* z, int
 }
 
 void build_tree(Tree& t, const double* x, const double* y, const double* z, hipStream_t st) {
+    // A first build reads the next level's size after every level and stops
+    // at the last one.  A rebuild queues the previous tree's level count
+    // plus one with no host read in between (an empty level costs only its
+    // launches); a tree that needs more sets kOvfLevels, and the build is
+    // done again level by level.
+    bool eager = t.levels_seen <= 0;
+    SetDev s0;
     for (int attempt = 0;; ++attempt) {
-        const int levels = std::max<int>(t.level_cap, 1);
-        build_queue(t, x, y, z, std::max(levels, 66), true, st);
+        const int levels = eager ? 66 : (int)std::min<int64_t>(66, t.levels_seen + 1);
+        build_queue(t, x, y, z, levels, eager, st);
         BT_HIP(hipMemcpyAsync(&t.host_ctl, t.ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, st));
         BT_HIP(hipMemcpyAsync(&t.host_stats, t.stats.p, sizeof(Stats), hipMemcpyDeviceToHost, st));
+        BT_HIP(hipMemcpyAsync(&s0, t.sets.p, sizeof(SetDev), hipMemcpyDeviceToHost, st));
         BT_HIP(hipStreamSynchronize(st));
         const Ctl& c = t.host_ctl;
         if (c.data_bad) fail(BTREE_EINVAL, "btree_build: non-finite particle coordinate");
         if (!c.overflow) break;
         if (attempt >= 6) fail(BTREE_ENOMEM, "btree_build: tree pools kept overflowing");
         // Grow what overflowed and build again.
+        if (c.overflow & kOvfLevels) eager = true;
         if (c.overflow & kOvfNodes) t.node_cap *= 2;
         if (c.overflow & kOvfCtab) t.ctab_cap *= 2;
         if (c.overflow & kOvfHist) t.hist_cap *= 2;
@@ -1322,8 +1331,6 @@ void build_tree(Tree& t, const double* x, const double* y, const double* z, hipS
     t.max_leaf = c.max_leaf;
     t.oversized = c.oversized;
     t.levels_seen = c.levels;
-    SetDev s0;
-    BT_HIP(hipMemcpy(&s0, t.sets.p, sizeof(SetDev), hipMemcpyDeviceToHost));
     t.root_code = s0.root;
     for (int k = 0; k < 6; ++k) t.rootbox[k] = s0.box[k];
 }

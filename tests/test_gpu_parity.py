@@ -349,6 +349,37 @@ def test_deterministic(prec):
 
 
 @pytest.mark.parametrize("prec", PRECS)
+def test_rebuild_deeper_than_before(prec):
+    """A rebuild queues the previous tree's level count plus one with no host
+    read between levels; a tree that needs more levels is built again level
+    by level.  A one-level tree (uniform set, s = 512), then a Plummer set
+    whose tree is deeper: same lists and tree depth as a fresh build."""
+    from paper_1910_02639_amd import btree
+    import torch
+    xu, yu, zu, hu = W.uniform_cube(20_000, 13, 64.0)
+    xp, yp, zp, hp = W.plummer(60_000, 14)
+    U = to_dev(xu, yu, zu, hu)
+    Pd = to_dev(xp, yp, zp, hp)
+    with btree.BTree(Pd[0], Pd[1], Pd[2], bucket_size=512, precision=prec) as fresh:
+        depth_p = fresh.stats()["depth"]
+    with btree.BTree(U[0], U[1], U[2], bucket_size=512, precision=prec) as t:
+        assert t.stats()["depth"] == 1
+        assert depth_p >= 3  # more than the one level queued beyond the last tree's
+        t.rebuild(Pd[0], Pd[1], Pd[2])
+        assert t.stats()["depth"] == depth_p
+        c, o, nb = t.find(Pd[3])
+        torch.cuda.synchronize()
+        assert_same_lists((c.cpu().numpy(), o.cpu().numpy(), nb.cpu().numpy()),
+                          oracle.lists(xp, yp, zp, hp))
+        t.rebuild(U[0], U[1], U[2])
+        assert t.stats()["depth"] == 1
+        c, o, nb = t.find(U[3])
+        torch.cuda.synchronize()
+        assert_same_lists((c.cpu().numpy(), o.cpu().numpy(), nb.cpu().numpy()),
+                          oracle.lists(xu, yu, zu, hu))
+
+
+@pytest.mark.parametrize("prec", PRECS)
 def test_rebuild_reuses_handle(prec):
     """btree_rebuild over a different set (and size) gives that set's lists;
     phase timers accumulate across rebuilds."""
