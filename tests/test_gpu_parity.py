@@ -134,7 +134,10 @@ def test_exhaustive_spans(prec):
 
 
 @pytest.mark.parametrize("name,s,kw", [("U10k", 64, {}), ("P60k", 32, {}),
-                                       ("P60k", 16, {"beta": 0.2}), ("L1M", 128, {})])
+                                       ("P60k", 16, {"beta": 0.2}), ("L1M", 128, {}),
+                                       ("P60k", 32, {"alpha": 0.25, "beta": 0.8}),
+                                       ("P60k", 64, {"alpha": 1.0, "beta": 0.3}),
+                                       ("U10k", 16, {"alpha": 0.125, "beta": 0.9})])
 def test_tree_matches_algorithm1(name, s, kw):
     """Integer tree shape (leaf sizes, depths, members, b per cell) equals the
     oracle's recursive Algorithm 1, leaf by leaf in depth-first order."""
@@ -164,6 +167,26 @@ def test_tree_matches_algorithm1(name, s, kw):
     for l in range(ref.n_leaves):
         a = np.sort(order[off[l]:off[l + 1]])
         assert np.array_equal(a, ref.members[off[l]:off[l + 1]]), l
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_parameter_grid_all_rows(prec):
+    """The lists do not depend on s, beta or alpha (the tuner's axes, Eq. 4):
+    every row of a 60k Plummer set against the oracle on a grid of them."""
+    from paper_1910_02639_amd import btree
+    import torch
+    x, y, z, h = W.plummer(60_000, 23)
+    dx, dy, dz, dh = to_dev(x, y, z, h)
+    for s_ in (16, 64, 256):
+        for beta in (0.3, 0.9):
+            for alpha in (0.125, 1.0):
+                log("grid", prec, s_, beta, alpha)
+                with btree.BTree(dx, dy, dz, bucket_size=s_, beta=beta, alpha=alpha,
+                                 precision=prec) as t:
+                    c, o, nb = t.find(dh)
+                    torch.cuda.synchronize()
+                    assert_all_rows(x, y, z, h, c.cpu().numpy(), o.cpu().numpy(),
+                                    nb.cpu().numpy(), "grid %d/%g/%g" % (s_, beta, alpha))
 
 
 def _lattice_expected_counts(m=100):
