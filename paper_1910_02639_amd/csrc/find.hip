@@ -1658,10 +1658,11 @@ __global__ __launch_bounds__(kWG) void k_place(const int32_t* __restrict__ count
 // the candidates and puts its hits after those of the lower wavefronts
 // (ascending original index) into a shared-memory image of the item's rows,
 // as 16-bit candidate numbers; then each wavefront copies whole rows out
-// with consecutive lanes on consecutive entries, so that every line leaves
-// the L2 whole (rows stored lane by lane reach HBM as partial lines, at a
-// fraction of the bandwidth).  Rows longer than the image go through it in
-// windows of kRowBuf entries.  A row is written only when its words hold
+// with consecutive lanes on consecutive entries, so that the lines inside a
+// row are written together and leave the L2 whole (only a row's two end
+// lines are partial; rows stored lane by lane, 16 bytes of 64 different rows
+// per store, took 1.5-2 times as long).  Rows longer than the image go
+// through it in windows of kRowBuf entries.  A row is written only when its words hold
 // exactly the count pass 1 recorded, so every store stays inside the row's
 // own range of the CSR.
 __global__ __launch_bounds__(kWG) void k_expand(const Chunk* __restrict__ chunks,
