@@ -653,8 +653,14 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     constexpr int kLPre = (kSMax + LMAX) / 2;
     uint16_t* const s_perm = reinterpret_cast<uint16_t*>(s_walk);
     static_assert(2 * (kSMax + LMAX) >= CMAX, "permutation must fit the walk area");
-    __shared__ int32_t s_bcnt[kBuckets];  // bucket sizes, then bucket starts
-    __shared__ int32_t s_bcur[kBuckets];  // placement cursors, then bucket ends
+    // Bucket sizes, then bucket starts; placement cursors, then bucket ends.
+    // Once the test is over (after a barrier) the density form keeps its
+    // per-wavefront sums in the same memory.
+    __shared__ __align__(16) int32_t s_bk[2 * kBuckets];
+    int32_t* const s_bcnt = s_bk;
+    int32_t* const s_bcur = s_bk + kBuckets;
+    static_assert(2 * kBuckets * sizeof(int32_t) >= kWaves * 64 * sizeof(double),
+                  "the density sums must fit the bucket arrays");
     __shared__ int32_t s_qoff[64];
     __shared__ int64_t s_scan[kWaves + 1];
     __shared__ int s_nleaf, s_ovf, s_kmin, s_kmax, s_C, s_big, s_total, s_bits, s_rows_total;
@@ -1060,15 +1066,11 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     int hits = 0;
     unsigned long long conf = 0;   // FP64 confirmations, the same in every lane
     unsigned long long lconf = 0;  // ... counted per lane (words of the three-FMA test)
-    // (Density form: per-query sums of the wavefront's part, in LDS.)
-    double* s_dens = nullptr;
-    if constexpr (OUT == kOutDensity) {
-        __shared__ double s_dens_mem[kWaves][64];
-        s_dens = &s_dens_mem[0][0];
-    }
+    // (Density form: lane q's sum of query q's terms over the wavefront's
+    // part.)
+    double dacc = 0.0;
     if (small) {
         if (lane >= ch.cnt) s_cnt[w][lane] = 0;
-        if (OUT == kOutDensity && lane >= ch.cnt) s_dens[w * 64 + lane] = 0.0;
         for (int q = 0; q < ch.cnt; ++q) {
             const Q Qd = query(q);
             int hq = 0;
@@ -1085,7 +1087,7 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
                 }
             }
             if (lane == 0) s_cnt[w][q] = hq;
-            if (OUT == kOutDensity && lane == 0) s_dens[w * 64 + q] = dq;
+            if (OUT == kOutDensity && lane == q) dacc = dq;
         }
     }
     for (int kw = k0; !small && kw < k1; kw += 32) {
@@ -1227,50 +1229,72 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
     if (lane == 0 && conf) atomicAdd(&stats->ctr[stripe][kCtrConfirms], conf);
     if (!small) s_cnt[w][lane] = hits;
     if constexpr (OUT == kOutDensity) {
-        // The lane's hits in its block, in ascending index.
+        // The lane's hits in its part, in ascending index.
         if (!small) {
-            // Each neighbour's coordinates (and mass) are loaded one hit
-            // ahead of their use, so a load is in flight while the previous
-            // term is evaluated; the coordinates come from the tree-ordered
-            // copy (the entries' keys are tree positions).
+            // The words are taken four at a time (128 candidates): the loop
+            // over one block runs as long as its busiest lane, so larger
+            // blocks leave fewer lanes idle.  Each neighbour's coordinates
+            // (and mass) are loaded one hit ahead of their use, so a load is
+            // in flight while the previous term is evaluated; the coordinates
+            // come from the tree-ordered copy (the entries' keys are tree
+            // positions).  The terms are added in ascending candidate order.
+            static_assert(kMaxW % 4 == 0, "words are taken four at a time");
             double acc = 0.0;
-            const int wbase = kMaxW - nw;
+            const int wbase = kMaxW - nw;  // slots below it hold zeros
             const double hq = 0.5 * R;
 #pragma unroll
-            for (int i = 0; i < kMaxW; ++i) {
-                const int wi = i - wbase;
-                if (wi >= 0 && qv) {
-                    uint32_t word = wq[i];
-                    const int kb = k0 + 32 * wi;
-                    double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
-                    double mj = 1.0;
-                    if (word) {
-                        o = src[Ent<F32>::key(cand(kb + __clz(word)))];
-                        if (dout.mass) mj = dout.mass[(int)o.w];
+            for (int i = 0; i < kMaxW; i += 4) {
+                uint64_t wa = qv ? ((uint64_t)wq[i] << 32) | wq[i + 1] : 0ull;
+                uint64_t wb = qv ? ((uint64_t)wq[i + 2] << 32) | wq[i + 3] : 0ull;
+                const int kb = k0 + 32 * (i - wbase);  // the candidate of wa's top bit
+                // The block's next hit (its candidate number), or -1.
+                auto pop = [&]() -> int {
+                    const bool ua = wa != 0ull;
+                    const uint64_t x = ua ? wa : wb;
+                    if (x == 0ull) return -1;
+                    const int j = __clzll(x);
+                    const uint64_t bit = 0x8000000000000000ull >> j;
+                    if (ua) wa ^= bit;
+                    else wb ^= bit;
+                    return kb + j + (ua ? 0 : 64);
+                };
+                int k = pop();
+                double4 o = make_double4(0.0, 0.0, 0.0, 0.0);
+                double mj = 1.0;
+                if (k >= 0) {
+                    o = src[Ent<F32>::key(cand(k))];
+                    if (dout.mass) mj = dout.mass[(int)o.w];
+                }
+                while (k >= 0) {
+                    const int kn = pop();
+                    double4 on = o;
+                    double mn = mj;
+                    if (kn >= 0) {
+                        on = src[Ent<F32>::key(cand(kn))];
+                        if (dout.mass) mn = dout.mass[(int)on.w];
                     }
-                    while (word) {
-                        word &= ~(0x80000000u >> __clz(word));
-                        double4 on = o;
-                        double mn = mj;
-                        if (word) {
-                            on = src[Ent<F32>::key(cand(kb + __clz(word)))];
-                            if (dout.mass) mn = dout.mass[(int)on.w];
-                        }
-                        const double dx = __dsub_rn(qp.x, o.x), dy = __dsub_rn(qp.y, o.y);
-                        const double dz = __dsub_rn(qp.z, o.z);
-                        const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
-                                                    __dmul_rn(dz, dz));
-                        const double wv = sph_shape(d2, hq);
-                        acc += dout.mass ? __dmul_rn(mj, wv) : wv;
-                        o = on;
-                        mj = mn;
-                    }
+                    const double dx = __dsub_rn(qp.x, o.x), dy = __dsub_rn(qp.y, o.y);
+                    const double dz = __dsub_rn(qp.z, o.z);
+                    const double d2 = __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)),
+                                                __dmul_rn(dz, dz));
+                    const double wv = sph_shape(d2, hq);
+                    acc += dout.mass ? __dmul_rn(mj, wv) : wv;
+                    o = on;
+                    mj = mn;
+                    k = kn;
                 }
             }
-            s_dens[w * 64 + lane] = acc;
+            dacc = acc;
         }
     }
     __syncthreads();
+    if constexpr (OUT == kOutDensity) {
+        // Every wavefront is past its last use of the buckets: the other
+        // wavefronts' sums go there for wavefront 0.
+        double* const s_dens = reinterpret_cast<double*>(s_bk);
+        if (w != 0) s_dens[w * 64 + lane] = dacc;
+        __syncthreads();
+    }
     if constexpr (OUT != kOutRows) {
         // Counts (and densities: the wavefronts' parts added in order); no
         // rows.
@@ -1280,7 +1304,8 @@ __device__ __forceinline__ int sweep_item(const int ci, const Chunk ch,
             for (int k = 0; k < kWaves; ++k) c += s_cnt[k][lane];
             if (qv) counts[qidx] = c;
             if constexpr (OUT == kOutDensity) {
-                const double sum = ((s_dens[lane] + s_dens[64 + lane]) + s_dens[128 + lane]) +
+                const double* const s_dens = reinterpret_cast<const double*>(s_bk);
+                const double sum = ((dacc + s_dens[64 + lane]) + s_dens[128 + lane]) +
                                    s_dens[192 + lane];
                 if (qv) dout.rho[qidx] = sph_density(sum, c, 0.5 * R);
             }

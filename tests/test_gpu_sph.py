@@ -83,6 +83,26 @@ def test_density_options(prec):
         _check_density(rho, c, want_rho, want_c, str(kw))
 
 
+_DENS_P8M = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_density_p8m_all_particles(prec):
+    """P8M (8M-particle Plummer sphere, masses drawn from [0.5, 2]) at the
+    parameters the timing runs use: every particle's count equals the
+    oracle's and every density lies within the summation-order bound."""
+    x, y, z, h = W.plummer(8_000_000, 0)
+    m = np.random.default_rng(52).uniform(0.5, 2.0, len(x))
+    log("density P8M", prec)
+    rho, c, st = _gpu_density(x, y, z, h, prec, mass=m, bucket_size=256, beta=0.8, alpha=0.25)
+    if not _DENS_P8M:
+        log("density P8M oracle")
+        _DENS_P8M["want"] = oracle.density(x, y, z, h, mass=m)
+    want_rho, want_c = _DENS_P8M["want"]
+    log("density P8M split items", st["split_items"], "exhaustive", st["brute_chunks"])
+    _check_density(rho, c, want_rho, want_c, "P8M " + prec)
+
+
 def test_density_matches_lists_and_repeats():
     """Counts of the fused pass equal the lists' counts; two runs give the
     same bytes; a zero-h particle has density 0."""
@@ -119,6 +139,31 @@ def test_adapt_h_equals_oracle(prec, gen, T, tol, scale):
     dx, dy, dz, dh = to_dev(x, y, z, h0)
     with btree.BTree(dx, dy, dz, bucket_size=64, precision=prec) as t:
         c, it = t.adapt_h(dh, T, tol, 60)
+        torch.cuda.synchronize()
+    assert it == want_it
+    assert np.array_equal(c.cpu().numpy().astype(np.int64), want_c)
+    assert np.array_equal(dh.cpu().numpy(), want_h), "h differs from the oracle's"
+
+
+_ADAPT_1M = {}
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_adapt_h_plummer_1m(prec):
+    """A 1M-particle Plummer sphere from 0.7 h to 100 +- 3 neighbours: the
+    same rounds, counts and h, bit for bit, as the oracle's adaptation."""
+    import torch
+    from paper_1910_02639_amd import btree
+    x, y, z, h = W.plummer(1_000_000, 3)
+    h0 = h * 0.7
+    if not _ADAPT_1M:
+        log("adapt_h 1M oracle")
+        _ADAPT_1M["want"] = oracle.adapt_h(x, y, z, h0, 100.0, 3.0, 60)
+    want_h, want_c, want_it = _ADAPT_1M["want"]
+    log("adapt_h 1M", prec, "rounds", want_it)
+    dx, dy, dz, dh = to_dev(x, y, z, h0)
+    with btree.BTree(dx, dy, dz, bucket_size=128, precision=prec) as t:
+        c, it = t.adapt_h(dh, 100.0, 3.0, 60)
         torch.cuda.synchronize()
     assert it == want_it
     assert np.array_equal(c.cpu().numpy().astype(np.int64), want_c)
