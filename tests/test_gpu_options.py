@@ -131,3 +131,22 @@ def test_octree_lists(prec):
         log("octree lists", name, prec)
         got = _lists(x, y, z, h, prec, bucket_size=s, octree=True)
         assert_same_lists(got, oracle.lists(x, y, z, h))
+
+
+def test_octree_and_exclude_self_p8m_all_rows():
+    """P8M (8M-particle Plummer sphere) at the b-tree/octree comparison's
+    bucket size: the octree's lists (depth 9) equal the oracle's row for
+    row, and the b-tree's exclude_self lists equal them less each row's own
+    index."""
+    from tests.helpers import assert_all_rows
+    x, y, z, h = W.plummer(8_000_000, 0)
+    log("octree P8M")
+    c, o, nb, st = _lists(x, y, z, h, "fp32", bucket_size=256, octree=True)
+    log("octree P8M depth", st["depth"], "split", st["split_items"])
+    assert st["depth"] > 3 and st["b_hist"] == {2: st["n_internal"]}
+    assert_all_rows(x, y, z, h, c, o, nb, "octree P8M")
+    log("exclude_self P8M")
+    got = _lists(x, y, z, h, "fp32", bucket_size=256, beta=0.8, exclude_self=True)
+    want = drop_self(c, o, nb)
+    del c, o, nb
+    assert_same_lists(got, want)
