@@ -264,6 +264,7 @@ struct Ctl {
     uint32_t queue;             // next search work item (atomic)
     uint32_t nbrute;            // work items on the exhaustive path (atomic)
     uint32_t nsplit2, nsplit3;  // units left for the second and third split levels (atomic)
+    uint32_t split_take[3];     // next unit of each split level to start (atomic)
     uint32_t nbunits;           // exhaustive-path units after regrouping by set
     uint32_t nbtasks;           // exhaustive count-pass tasks (unit x span of its set)
     int64_t bspan;              // candidates per exhaustive count-pass task

@@ -1536,6 +1536,9 @@ __device__ __forceinline__ void to_brute(const Chunk q, const double4* __restric
 // overflow too.  In larger sets a sweep of the whole set by one workgroup
 // would be long, so units there go down to single queries first.
 constexpr int64_t kDenseSet = 32768;
+// Split levels from this one take their units from a counter; level 1
+// keeps a fixed stride over its list (measured faster there).
+constexpr int kDynFrom = 2;
 
 template <bool F32, int LEVEL, int OUT>
 __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ in,
@@ -1568,13 +1571,23 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
     constexpr int kParts = LEVEL == 1 ? 1 : LEVEL == 2 ? kGroup / kSubGroup : kSubGroup;
     const uint32_t nin = LEVEL == 1 ? ctl->nsplit : LEVEL == 2 ? ctl->nsplit2 : ctl->nsplit3;
     const uint64_t units = (uint64_t)nin * kParts;
-    for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
+    // The parts of levels 2 and 3 differ widely in cost, so there a
+    // workgroup takes the next unit from a counter when it is done with one
+    // (a fixed stride over the list left a few workgroups with long chains
+    // of heavy units).
+    constexpr bool kDynamic = LEVEL >= kDynFrom;
+    __shared__ uint32_t s_take;
+    for (uint64_t us = blockIdx.x;; us += gridDim.x) {
+        __syncthreads();  // the previous unit is done with the shared memory
+        if (kDynamic && threadIdx.x == 0) s_take = atomicAdd(&ctl->split_take[LEVEL - 1], 1u);
+        if (kDynamic) __syncthreads();
+        const uint64_t u = kDynamic ? (uint64_t)s_take : us;
+        if (u >= units) break;
         const Chunk src = in[u / kParts];
         const int q0 = (int)(u % kParts) * kPart;
         if (q0 >= src.cnt) continue;  // uniform: the unit is empty
         const Chunk unit{src.beg + q0, min(kPart, src.cnt - q0), src.set, 0};
         const int64_t nset = sets[unit.set].n;
-        __syncthreads();  // the previous unit is done with the shared memory
         if (LEVEL == 1 && nset <= kDenseSet && src.pad != kNoCount && 4 * (int64_t)src.pad > nset) {
             to_brute(unit, pos, soff, ctl, brute, bcnt, stats);
             continue;
@@ -2087,6 +2100,7 @@ __global__ void k_find_reset(Ctl* __restrict__ ctl, Stats* __restrict__ stats,
         ctl->nsplit = 0;
         ctl->nsplit2 = 0;
         ctl->nsplit3 = 0;
+        for (int k = 0; k < 3; ++k) ctl->split_take[k] = 0;
         ctl->nbrute = 0;
         ctl->nbunits = 0;
         ctl->nbtasks = 0;
