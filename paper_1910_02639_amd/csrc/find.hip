@@ -1572,16 +1572,22 @@ __global__ __launch_bounds__(kWG) void k_sweep_split(const Chunk* __restrict__ i
     const uint32_t nin = LEVEL == 1 ? ctl->nsplit : LEVEL == 2 ? ctl->nsplit2 : ctl->nsplit3;
     const uint64_t units = (uint64_t)nin * kParts;
     // The parts of levels 2 and 3 differ widely in cost, so there a
-    // workgroup takes the next unit from a counter when it is done with one
+    // workgroup that is done with a unit takes the next one from a counter
     // (a fixed stride over the list left a few workgroups with long chains
-    // of heavy units).
+    // of heavy units).  Every workgroup's first unit is its own index, so a
+    // short list costs no atomics.
     constexpr bool kDynamic = LEVEL >= kDynFrom;
     __shared__ uint32_t s_take;
+    bool first = true;
     for (uint64_t us = blockIdx.x;; us += gridDim.x) {
         __syncthreads();  // the previous unit is done with the shared memory
-        if (kDynamic && threadIdx.x == 0) s_take = atomicAdd(&ctl->split_take[LEVEL - 1], 1u);
-        if (kDynamic) __syncthreads();
-        const uint64_t u = kDynamic ? (uint64_t)s_take : us;
+        uint64_t u = us;
+        if (kDynamic && !first) {
+            if (threadIdx.x == 0) s_take = atomicAdd(&ctl->split_take[LEVEL - 1], 1u);
+            __syncthreads();
+            u = (uint64_t)gridDim.x + s_take;
+        }
+        first = false;
         if (u >= units) break;
         const Chunk src = in[u / kParts];
         const int q0 = (int)(u % kParts) * kPart;
